@@ -1,0 +1,300 @@
+"""Pins for the FP64 oracle: each check compares it with something other than
+itself (brute force, explicit 2-D containment, closed forms on jitter-free grids,
+hand-derived values, invariances of the definition)."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import kuhn_mesh, pinhole_rays, random_interior_rays, ao_rays, tri_geometry
+from synth.kuhn import random_spheres
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---- Algorithm 1 against explicit containment ---------------------------------
+
+def _orient(a, b, c):
+    return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0])
+
+
+def _edge(a, b):
+    """Orientation of (a, b, origin); exactly zero when the origin is on line ab
+    through the origin-anchored form a x b."""
+    return a[0] * b[1] - a[1] * b[0]
+
+
+def _containing_slots(q, strict=True):
+    """Slots e such that the face with q3 in place of q[e] holds the origin
+    (counter-clockwise, closed unless ``strict``)."""
+    out = []
+    for e in range(3):
+        f = [q[0], q[1], q[2]]
+        f[e] = q[3]
+        o = [_edge(f[0], f[1]), _edge(f[1], f[2]), _edge(f[2], f[0])]
+        if (all(v > 0 for v in o) if strict else all(v >= 0 for v in o)):
+            out.append(e)
+    return out
+
+
+def _random_face(rng, scale):
+    while True:
+        q = rng.normal(size=(3, 2)) * scale
+        o = [_orient(q[0], q[1], (0, 0)), _orient(q[1], q[2], (0, 0)), _orient(q[2], q[0], (0, 0))]
+        if all(v > 0 for v in o):
+            return q
+        if all(v < 0 for v in o):
+            return q[[0, 2, 1]]
+
+
+def test_exit_face_matches_containment_random():
+    rng = np.random.default_rng(11)
+    checked = 0
+    for it in range(20000):
+        scale = 10.0 ** rng.uniform(-4, 1)
+        q = np.zeros((4, 2))
+        q[:3] = _random_face(rng, scale)
+        q[3] = rng.normal(size=2) * scale * 10.0 ** rng.uniform(-1, 1)
+        strict = _containing_slots(q)
+        assert len(strict) <= 1
+        if strict:
+            assert oracle.get_exit_face(q) == strict[0]
+            checked += 1
+    assert checked > 19000
+
+
+def test_exit_face_sign_exhaustive():
+    """q3 on both sides of (and exactly on) each line origin-q_i."""
+    rng = np.random.default_rng(5)
+    for it in range(3000):
+        q = np.zeros((4, 2))
+        q[:3] = _random_face(rng, 1.0)
+        for i, s in itertools.product(range(3), (-2.0, -0.5, 0.5, 2.0)):
+            for eps in (-1e-3, 0.0, 1e-3):
+                perp = np.array([-q[i][1], q[i][0]])
+                q[3] = s * q[i] + eps * perp
+                e = oracle.get_exit_face(q)
+                assert e in _containing_slots(q, strict=False), (q, e)
+
+
+# ---- the oracle's frame ----------------------------------------------------------
+
+def test_onb_orthonormal_right_handed():
+    rng = np.random.default_rng(2)
+    ns = list(rng.normal(size=(2000, 3))) + [np.array(v, float) for v in
+                                               ([0, 0, 1], [0, 0, -1], [1, 0, 0], [0, -1, 0],
+                                                [1e-12, 0, -1], [0, 1e-9, 1])]
+    for n in ns:
+        n = n / np.linalg.norm(n)
+        b1, b2 = oracle.onb(n)
+        M = np.stack([b1, b2, n])
+        assert np.allclose(M @ M.T, np.eye(3), atol=1e-12)
+        assert np.allclose(np.cross(b1, b2), n, atol=1e-12)
+
+
+# ---- hand-derived golden values --------------------------------------------------
+
+def _read_golden(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        lhs, rhs = line.split("|")
+        rows.append(([float(x) for x in lhs.split()], [float(x) for x in rhs.split()]))
+    return rows
+
+
+def test_golden_cube_box():
+    m = kuhn_mesh(1, jitter=0.0)
+    cf = (m.nbrs < 0).astype(np.uint8)          # every boundary face is scene geometry
+    om = oracle.OracleMesh(m.points, m.tets, m.nbrs, cf)
+    assert om.ntri == 12
+    rows = _read_golden("kuhn_cube_box.txt")
+    inp = np.array([r[0] for r in rows])
+    exp = np.array([r[1] for r in rows])
+    r = om.trace(inp[:, 0:3], inp[:, 3:6], inp[:, 6])
+    assert r["tri"].tolist() == exp[:, 0].astype(int).tolist()
+    hit = exp[:, 0] >= 0
+    assert np.allclose(r["t"][hit], exp[hit, 1], rtol=1e-14, atol=0)
+    assert np.allclose(r["bary"][hit], exp[hit, 2:4], atol=1e-14)
+    assert r["steps"].tolist() == exp[:, 4].astype(int).tolist()
+    assert r["start"].tolist() == exp[:, 5].astype(int).tolist()
+
+
+# ---- against brute force ---------------------------------------------------------
+
+def _check_vs_brute(om, points, orig, dirs, tmax=None, start_face=None, t_rtol=1e-12,
+                    bary_tol=1e-10):
+    r = om.trace(orig, dirs, tmax, start_face=start_face)
+    bt, btt, bb = oracle.brute_closest_hit(points, om.tri_verts, orig, dirs, tmax, exclude=start_face)
+    assert np.all(r["tri"] >= -1), np.unique(r["tri"])
+    same = r["tri"] == bt
+    # ties between triangles sharing an edge may go either way; the brute force
+    # then has a second hit at the same t
+    if not np.all(same):
+        bad = np.nonzero(~same)[0]
+        for i in bad:
+            assert r["tri"][i] >= 0 and bt[i] >= 0, (i, r["tri"][i], bt[i])
+            assert abs(r["t"][i] - btt[i]) <= 1e-12
+            # the oracle's triangle is also hit at that t
+            tv = om.tri_verts[r["tri"][i]]
+            P = points.astype(np.float64)
+            A, B, Cc = P[tv[0]], P[tv[1]], P[tv[2]]
+            h = orig[i].astype(np.float64) + btt[i] * dirs[i].astype(np.float64)
+            w = np.linalg.lstsq(np.stack([B - A, Cc - A], 1), h - A, rcond=None)[0]
+            assert w.min() > -1e-9 and w.sum() < 1 + 1e-9
+    h = same & (bt >= 0)
+    assert np.all(np.abs(r["t"][h] - btt[h]) <= t_rtol * np.abs(btt[h]))
+    assert np.all(np.abs(r["bary"][h] - bb[h]) <= bary_tol)
+    return r, same.mean()
+
+
+def test_tiny_primary_vs_brute(tiny_mesh, tiny_oracle):
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 64, 64, 60.0)
+    r, frac = _check_vs_brute(tiny_oracle, tiny_mesh.points, o, d)
+    assert frac == 1.0
+    assert np.all(r["tri"] >= 0)          # the camera looks straight at the sphere
+
+
+@pytest.mark.parametrize("n,jit,nsph,seed", [(4, 0.1, 2, 1), (8, 0.1, 5, 2), (8, 0.0, 3, 3),
+                                             (6, 0.1, 1, 4)])
+def test_random_rays_vs_brute(n, jit, nsph, seed):
+    m = kuhn_mesh(n, jitter=jit, seed=seed, spheres=random_spheres(nsph, seed=seed, r_lo=0.1, r_hi=0.3))
+    om = oracle.OracleMesh.from_kuhn(m)
+    o, d = random_interior_rays(3000, seed)
+    tm = np.random.default_rng(seed).uniform(0.05, 1.5, size=3000).astype(np.float32)
+    tm[::3] = np.inf
+    _check_vs_brute(om, m.points, o, d, tm)
+
+
+def test_secondary_rays_vs_brute(tiny_mesh, tiny_oracle):
+    """AO rays leaving from primary hits (start face given) against brute force
+    with the start face excluded."""
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 32, 32, 60.0)
+    r = tiny_oracle.trace(o, d)
+    hit = r["tri"] >= 0
+    hp = o[hit].astype(np.float64) + r["t"][hit, None] * d[hit].astype(np.float64)
+    nrm, _ = tri_geometry(tiny_mesh.points, tiny_oracle.tri_verts[r["tri"][hit]])
+    ao, ad, atm, parent = ao_rays(hp, nrm, d[hit], k=8, seed=3, tmax=0.1)
+    sf = r["tri"][hit][parent]
+    _check_vs_brute(tiny_oracle, tiny_mesh.points, ao, ad, atm, start_face=sf, t_rtol=1e-9,
+                    bary_tol=1e-8)
+
+
+# ---- closed forms on jitter-free grids ------------------------------------------
+
+def _planes_crossed(o, h, n):
+    """Hyperplanes x_i = k/n and x_i - x_j = k/n crossed strictly between o and h."""
+    cnt = 0
+    fs = [lambda x, i=i: x[..., i] for i in range(3)]
+    fs += [lambda x, i=i, j=j: x[..., i] - x[..., j] for i, j in ((0, 1), (0, 2), (1, 2))]
+    for f in fs:
+        a, b = n * f(o), n * f(h)
+        lo, hi = np.minimum(a, b), np.maximum(a, b)
+        cnt = cnt + np.maximum(0, np.ceil(hi - 1e-7) - np.floor(lo + 1e-7) - 1).astype(int)
+    return cnt
+
+
+def test_step_count_closed_form():
+    # n a power of two keeps every grid coordinate k/n exact in float32, so the
+    # tet faces lie exactly on the planes counted below
+    n = 8
+    m = kuhn_mesh(n, jitter=0.0, spheres=[[0.5, 0.45, 0.55, 0.3], [0.2, 0.8, 0.3, 0.15]])
+    om = oracle.OracleMesh.from_kuhn(m)
+    o, d = random_interior_rays(4000, 21)
+    r = om.trace(o, d)
+    bt, btt, _ = oracle.brute_closest_hit(m.points, om.tri_verts, o, d)
+    hit = bt >= 0
+    assert hit.sum() > 800
+    h = o[hit].astype(np.float64) + btt[hit, None] * d[hit].astype(np.float64)
+    expect = _planes_crossed(o[hit].astype(np.float64), h, n)
+    assert np.array_equal(r["steps"][hit], expect)
+
+
+def test_axis_parallel_t_closed_form():
+    n = 16
+    m = kuhn_mesh(n, jitter=0.0)           # sphere r = 0.35 at the centre
+    om = oracle.OracleMesh.from_kuhn(m)
+    rng = np.random.default_rng(8)
+    k = 400
+    o = np.stack([rng.uniform(0.2, 0.8, k), rng.uniform(0.2, 0.8, k), rng.uniform(0.01, 0.1, k)], 1)
+    o = o.astype(np.float32)
+    d = np.tile(np.array([[0, 0, 1]], np.float32), (k, 1))
+    r = om.trace(o, d)
+    ci = np.floor(o[:, 0].astype(np.float64) * n).astype(int)
+    cj = np.floor(o[:, 1].astype(np.float64) * n).astype(int)
+    ck = np.floor(o[:, 2].astype(np.float64) * n).astype(int)
+    for i in range(k):
+        col = m.inside[ci[i], cj[i]]
+        change = [z for z in range(ck[i], n - 1) if col[z] != col[z + 1]]
+        if not change:
+            assert r["tri"][i] == -1
+            continue
+        zhit = (change[0] + 1) / n
+        assert r["tri"][i] >= 0
+        assert abs(r["t"][i] - (zhit - float(o[i, 2]))) <= 1e-13
+
+
+# ---- invariances of the definition -----------------------------------------------
+
+def test_independent_of_source_tet(tiny_mesh, tiny_oracle):
+    o, d = random_interior_rays(2000, 31)
+    base = tiny_oracle.trace(o, d, source_tet=0)
+    for src in (777, 12345, tiny_mesh.n_tets - 1):
+        r = tiny_oracle.trace(o, d, source_tet=src)
+        assert np.array_equal(r["tri"], base["tri"])
+        h = base["tri"] >= 0
+        assert np.array_equal(r["t"][h], base["t"][h])
+
+
+def test_early_out_changes_nothing(tiny_mesh, tiny_oracle):
+    o, d = random_interior_rays(3000, 41)
+    tm = np.random.default_rng(1).uniform(0.0, 0.4, 3000).astype(np.float32)
+    a = tiny_oracle.trace(o, d, tm, early_out=True)
+    b = tiny_oracle.trace(o, d, tm, early_out=False)
+    assert np.array_equal(a["tri"], b["tri"])
+    h = a["tri"] >= 0
+    assert np.array_equal(a["t"][h], b["t"][h])
+    assert a["steps"].sum() < b["steps"].sum()
+
+
+def test_locate_contains_point(tiny_mesh, tiny_oracle):
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.0, 1.0, size=(3000, 3)).astype(np.float32)
+    t = tiny_oracle.locate(x)
+    assert np.all(t >= 0)
+    P = tiny_mesh.points.astype(np.float64)
+    V = P[tiny_mesh.tets[t]]
+    X = x.astype(np.float64)
+    for j in range(4):   # x is on the inner side of every face (closed)
+        f = [s for s in range(4) if s != j]
+        A, B, Cc, W = V[:, f[0]], V[:, f[1]], V[:, f[2]], V[:, j]
+        nrm = np.cross(B - A, Cc - A)
+        sw = np.einsum("ij,ij->i", nrm, W - A)
+        sx = np.einsum("ij,ij->i", nrm, X - A)
+        assert np.all(sx * np.sign(sw) >= -1e-15)
+    out = tiny_oracle.locate(np.array([[1.5, 0.5, 0.5], [-0.1, 0.2, 0.2]], np.float32))
+    assert out.tolist() == [-1, -1]
+
+
+def test_invalid_rays_and_start_tet(tiny_mesh, tiny_oracle):
+    o = np.array([[0.5, 0.5, 0.05]] * 3 + [[2.0, 0.5, 0.5]], np.float32)
+    d = np.array([[0, 0, 0], [np.nan, 0, 1], [0, 0, 1], [0, 0, 1]], np.float32)
+    r = tiny_oracle.trace(o, d)
+    assert r["tri"].tolist()[:2] == [-3, -3] and r["tri"][2] >= 0 and r["tri"][3] == -3
+    # a caller-supplied start tet gives the same answer as location
+    st = tiny_oracle.locate(o[2:3])
+    r2 = tiny_oracle.trace(o[2:3], d[2:3], start_tet=st)
+    assert r2["tri"][0] == r["tri"][2] and r2["t"][0] == r["t"][2]
+
+
+def test_inconsistent_mesh_rejected():
+    m = kuhn_mesh(4, jitter=0.0, spheres=[[0.5, 0.5, 0.5, 0.3]])
+    cf = m.cflag.copy()
+    t, j = np.argwhere(cf)[0]
+    cf[t, j] = 0          # break the symmetry of one flag: the other side still has it
+    with pytest.raises(ValueError):
+        oracle.OracleMesh(m.points, m.tets, m.nbrs, cf)

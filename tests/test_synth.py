@@ -1,0 +1,110 @@
+"""Input generator checks: mesh invariants of the Kuhn-grid scenes and ray sets."""
+import numpy as np
+import pytest
+
+from synth import kuhn_mesh, config_mesh, pinhole_rays, ao_rays, precision_rays
+from synth.kuhn import tet_volumes6, random_spheres
+from synth.rays import tile_order
+
+
+def _face_table(tets):
+    T = tets.shape[0]
+    faces = np.sort(np.stack([np.delete(tets, j, axis=1) for j in range(4)], axis=1), axis=2)
+    return faces.reshape(T * 4, 3)
+
+
+@pytest.mark.parametrize("n,jit", [(1, 0.0), (2, 0.1), (4, 0.1), (7, 0.0), (8, 0.1)])
+def test_kuhn_counts_and_links(n, jit):
+    m = kuhn_mesh(n, jitter=jit, seed=3, spheres=random_spheres(3, seed=n))
+    assert m.n_tets == 6 * n ** 3
+    assert m.n_points == (n + 1) ** 3
+    assert np.all(tet_volumes6(m.points, m.tets) > 0)
+    # neighbours: found by face hashing, independently of the construction
+    faces = _face_table(m.tets)
+    key = (faces[:, 0].astype(np.int64) * m.n_points + faces[:, 1]) * m.n_points + faces[:, 2]
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    same = np.nonzero(ks[1:] == ks[:-1])[0]
+    expect = np.full(m.n_tets * 4, -1, np.int64)
+    a, b = order[same], order[same + 1]
+    expect[a] = b // 4
+    expect[b] = a // 4
+    assert np.array_equal(expect.reshape(-1, 4), m.nbrs)
+    # flags symmetric, never on the cube boundary
+    fl = m.cflag.reshape(-1)
+    assert np.array_equal(fl[a], fl[b])
+    assert not np.any(fl[expect < 0])
+    # Euler characteristic of a ball
+    E = set()
+    for i in range(4):
+        for k in range(i + 1, 4):
+            lo = np.minimum(m.tets[:, i], m.tets[:, k]).astype(np.int64)
+            hi = np.maximum(m.tets[:, i], m.tets[:, k]).astype(np.int64)
+            E.update((lo * m.n_points + hi).tolist())
+    F = len(np.unique(key))
+    assert m.n_points - len(E) + F - m.n_tets == 1
+
+
+def test_tiny_config_counts(tiny_mesh):
+    assert tiny_mesh.n_tets == 24576 and tiny_mesh.n_points == 4913
+    # sphere r = 0.35 at the centre of a 16^3 grid: 576 inside/outside cell faces,
+    # each split into two triangles
+    assert tiny_mesh.n_constrained_faces() == 1152
+    # jitter is +-0.1 cell and keeps volumes positive; the smallest 6*volume of a
+    # Kuhn tet of side h is h^3, jitter shrinks it by well under half
+    v = tet_volumes6(tiny_mesh.points, tiny_mesh.tets)
+    assert v.min() > 0.4 / 16 ** 3
+
+
+def test_jitter_only_moves_interior_vertices():
+    m0 = kuhn_mesh(5, jitter=0.0)
+    m1 = kuhn_mesh(5, jitter=0.1, seed=9)
+    d = np.abs(m1.points - m0.points).max(axis=1)
+    onb = np.any((m0.points == 0) | (m0.points == 1), axis=1)
+    assert np.all(d[onb] == 0)
+    assert np.all(d[~onb] > 0) and d.max() <= 0.1 / 5 + 1e-7
+
+
+def test_pinhole_rays_shape_and_tiles():
+    o, d, pix = pinhole_rays((0.5, 0.5, 0.05), 64, 64, 60.0)
+    assert o.shape == (4096, 3) and d.shape == (4096, 3)
+    assert np.allclose(np.linalg.norm(d, axis=1), 1, atol=1e-6)
+    assert sorted(pix.tolist()) == list(range(4096))
+    # first 64 rays form one 8x8 tile
+    assert set((pix[:64] % 64).tolist()) == set(range(8))
+    assert set((pix[:64] // 64).tolist()) == set(range(8))
+    # horizontal FOV: the extreme columns are +-30 degrees off axis (minus half a pixel)
+    row = d[np.argsort(pix)].reshape(64, 64, 3)[32]
+    ang = np.degrees(np.arctan2(np.abs(row[:, 0]), row[:, 2]))
+    assert 29.0 < ang.max() < 30.0
+    assert np.array_equal(tile_order(3, 2, 1), np.arange(6))
+
+
+def test_ao_rays_hemisphere():
+    rng = np.random.default_rng(0)
+    hp = rng.random((50, 3))
+    nrm = rng.normal(size=(50, 3))
+    din = rng.normal(size=(50, 3))
+    o, d, tm, parent = ao_rays(hp, nrm, din, k=8, seed=1)
+    assert o.shape == (400, 3) and np.all(tm == np.float32(0.1))
+    n_side = -np.sign(np.einsum("ij,ij->i", nrm, din))[:, None] * nrm
+    cosv = np.einsum("ij,ij->i", d.astype(np.float64), n_side[parent] / np.linalg.norm(n_side[parent], axis=1, keepdims=True))
+    assert np.all(cosv > -1e-6)
+    # cosine-weighted: E[cos] = 2/3
+    assert abs(cosv.mean() - 2.0 / 3.0) < 0.05
+
+
+def test_precision_rays_mix(tiny_mesh):
+    o, d, kind = precision_rays(tiny_mesh.points, tiny_mesh.tets, tiny_mesh.cflag, n=2000, seed=4)
+    assert (kind == 1).sum() == 200 and (kind == 2).sum() == 200
+    assert np.allclose(np.linalg.norm(d, axis=1), 1, atol=1e-6)
+    assert np.all((o >= 0) & (o <= 1))
+
+
+def test_paper_config_spheres():
+    sp = random_spheres(20, seed=2)
+    assert sp.shape == (20, 4)
+    assert np.all((sp[:, :3] >= 0.15) & (sp[:, :3] <= 0.85))
+    assert np.all((sp[:, 3] >= 0.03) & (sp[:, 3] <= 0.12))
+    # the camera at (0.5, 0.5, 0.02) is outside every sphere
+    assert np.all(np.linalg.norm(sp[:, :3] - [0.5, 0.5, 0.02], axis=1) > sp[:, 3])
