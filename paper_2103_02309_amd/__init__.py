@@ -1,0 +1,15 @@
+"""tetrt: closest-hit ray traversal through a constrained tetrahedral mesh on
+MI355X (gfx950).
+
+The compute path is the C-ABI library ``libtetrt.so`` (HIP kernels and host
+packing, declared in ``include/tetrt.h``).  This package is its Python binding:
+the functions below carry the library's names and only marshal arguments;
+PyTorch supplies device memory and the current stream.
+"""
+from .binding import (TetRTError, Mesh, upload, tetmesh_upload, trace_closest, tetmesh_locate,
+                      tetmesh_tri_vertices, tetmesh_info, tetmesh_free, tm_last_error,
+                      tetrt_sfc_keys, library_path, RAY_MISS, RAY_STEP_CAP, RAY_INVALID)
+
+__all__ = ["TetRTError", "Mesh", "upload", "tetmesh_upload", "trace_closest", "tetmesh_locate",
+           "tetmesh_tri_vertices", "tetmesh_info", "tetmesh_free", "tm_last_error",
+           "tetrt_sfc_keys", "library_path", "RAY_MISS", "RAY_STEP_CAP", "RAY_INVALID"]

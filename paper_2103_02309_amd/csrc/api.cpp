@@ -1,0 +1,253 @@
+// C-ABI entry points declared in include/tetrt.h.
+#include <hip/hip_runtime_api.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "pack.h"
+#include "tetrt.h"
+
+struct tm_mesh_s {
+    tetrt::DevMesh dev{};
+    int device = 0;
+    int64_t np = 0, nt = 0, ntri = 0;
+    int32_t layout = 0, sfc = 0;
+    int64_t hot_bytes = 0, cold_bytes = 0;
+    std::vector<int32_t> tri_verts_user;  // host copy for tetmesh_tri_vertices
+    std::vector<void*> allocations;
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(TM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void release(tm_mesh_s* m) {
+    for (void* p : m->allocations) (void)hipFree(p);
+    m->allocations.clear();
+}
+
+// Copy a host vector into a new device buffer owned by the handle.
+template <class T>
+int upload_array(tm_mesh_s* m, const std::vector<T>& v, const T** out, int64_t* bytes_acc) {
+    size_t bytes = v.size() * sizeof(T);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes > 0 ? bytes : 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TM_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    m->allocations.push_back(p);
+    if (bytes > 0) {
+        e = hipMemcpy(p, v.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    }
+    *out = static_cast<const T*>(p);
+    *bytes_acc += int64_t(bytes);
+    return TM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tm_last_error(void) { return g_error.c_str(); }
+
+int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, const int32_t* nbrs,
+                   const uint8_t* cflag, int64_t n_tets, const tm_upload_opts* opts, tm_mesh* out) {
+    g_error.clear();
+    if (!out) return fail(TM_ERR_ARG, "tetmesh_upload: out is NULL");
+    *out = nullptr;
+    if (!points || !tets || !nbrs || !cflag)
+        return fail(TM_ERR_ARG, "tetmesh_upload: NULL input array");
+    if (n_tets < 1 || n_tets >= int64_t(0x7FFFFFFF))
+        return fail(TM_ERR_ARG, "tetmesh_upload: n_tets = %lld out of range [1, 2^31-1)",
+                    (long long)n_tets);
+    if (n_points < 4 || n_points >= int64_t(0x80000000LL))
+        return fail(TM_ERR_ARG, "tetmesh_upload: n_points = %lld out of range [4, 2^31)",
+                    (long long)n_points);
+    tm_upload_opts o = {TM_LAYOUT_TET20, TM_SFC_HILBERT, 1, 0};
+    if (opts) o = *opts;
+    if (o.layout != TM_LAYOUT_TET20)
+        return fail(TM_ERR_ARG, "tetmesh_upload: unsupported layout %d", o.layout);
+    if (o.sfc < TM_SFC_HILBERT || o.sfc > TM_SFC_NONE)
+        return fail(TM_ERR_ARG, "tetmesh_upload: unknown sfc %d", o.sfc);
+    if (o.seed_grid < 0 || o.seed_grid > 256)
+        return fail(TM_ERR_ARG, "tetmesh_upload: seed_grid %d out of range [0, 256]", o.seed_grid);
+
+    tetrt::PackedMesh pm;
+    std::string err;
+    int rc;
+    try {
+        rc = tetrt::pack_mesh(points, n_points, tets, nbrs, cflag, n_tets, o, &pm, &err);
+    } catch (const std::bad_alloc&) {
+        return fail(TM_ERR_OOM, "tetmesh_upload: host allocation failed while packing");
+    }
+    if (rc != TM_OK) return fail(rc, "tetmesh_upload: %s", err.c_str());
+
+    tm_mesh_s* m = new (std::nothrow) tm_mesh_s();
+    if (!m) return fail(TM_ERR_OOM, "tetmesh_upload: host allocation failed");
+    (void)hipGetDevice(&m->device);
+    m->np = pm.np;
+    m->nt = pm.nt;
+    m->ntri = pm.ntri;
+    m->layout = pm.layout;
+    m->sfc = pm.sfc;
+    int64_t hot = 0, cold = 0;
+    tetrt::DevMesh& d = m->dev;
+    if ((rc = upload_array(m, pm.vx, &d.vx, &hot)) || (rc = upload_array(m, pm.nb, &d.nb, &hot)) ||
+        (rc = upload_array(m, pm.pts4, &d.pts, &hot)) ||
+        (rc = upload_array(m, pm.tetv, &d.tetv, &cold)) ||
+        (rc = upload_array(m, pm.cfv, &d.cfv, &cold)) ||
+        (rc = upload_array(m, pm.cft, &d.cft, &cold)) ||
+        (rc = upload_array(m, pm.t_new2old, &d.t_new2old, &cold)) ||
+        (rc = upload_array(m, pm.t_old2new, &d.t_old2new, &cold)) ||
+        (rc = upload_array(m, pm.seed, &d.seed, &cold))) {
+        release(m);
+        delete m;
+        return rc;
+    }
+    for (int a = 0; a < 3; ++a) {
+        d.lo[a] = pm.lo[a];
+        d.inv_cell[a] = pm.inv_cell[a];
+    }
+    d.G = pm.G;
+    d.nt = int32_t(pm.nt);
+    d.np = int32_t(pm.np);
+    d.ntri = int32_t(pm.ntri);
+    m->hot_bytes = hot;
+    m->cold_bytes = cold;
+    m->tri_verts_user.swap(pm.tri_verts_user);
+    *out = m;
+    return TM_OK;
+}
+
+int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d_dir,
+                  const float* d_tmax, const int32_t* d_start_tet, const int32_t* d_start_face,
+                  int32_t* d_tri, float* d_t, float* d_bary, int32_t* d_hit_tets, int32_t* d_steps,
+                  const tm_trace_opts* opts, void* hip_stream) {
+    g_error.clear();
+    if (!m) return fail(TM_ERR_ARG, "trace_closest: NULL mesh");
+    if (n_rays < 0 || n_rays > int64_t(0x7FFFFFFF))
+        return fail(TM_ERR_ARG, "trace_closest: n_rays = %lld out of range [0, 2^31)",
+                    (long long)n_rays);
+    if (n_rays == 0) return TM_OK;
+    if (!d_orig || !d_dir || !d_tri || !d_t || !d_bary)
+        return fail(TM_ERR_ARG, "trace_closest: NULL required array");
+    if ((reinterpret_cast<uintptr_t>(d_bary) & 7) || (reinterpret_cast<uintptr_t>(d_hit_tets) & 7))
+        return fail(TM_ERR_ARG, "trace_closest: bary / hit_tets must be 8-byte aligned");
+    tm_trace_opts o = {0, 0, 0, 0};
+    if (opts) o = *opts;
+    if (o.max_steps < 0) return fail(TM_ERR_ARG, "trace_closest: negative max_steps");
+    if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
+        return fail(TM_ERR_ARG, "trace_closest: block must be 64, 128 or 256");
+    tetrt::RayArgs r;
+    r.orig = d_orig;
+    r.dir = d_dir;
+    r.tmax = d_tmax;
+    r.start_tet = d_start_tet;
+    r.start_face = d_start_face;
+    r.tri = d_tri;
+    r.t = d_t;
+    r.bary = d_bary;
+    r.hit_tets = d_hit_tets;
+    r.steps = d_steps;
+    r.n = n_rays;
+    r.max_steps = o.max_steps > 0 ? o.max_steps : 65536;
+    hipError_t e = tetrt::launch_trace(m->dev, r, o.block ? o.block : 256,
+                                       static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "trace_closest: kernel launch");
+    return TM_OK;
+}
+
+int tetmesh_locate(tm_mesh m, int64_t n, const float* d_pts, int32_t* d_tet, void* hip_stream) {
+    g_error.clear();
+    if (!m) return fail(TM_ERR_ARG, "tetmesh_locate: NULL mesh");
+    if (n < 0 || n > int64_t(0x7FFFFFFF))
+        return fail(TM_ERR_ARG, "tetmesh_locate: n = %lld out of range [0, 2^31)", (long long)n);
+    if (n == 0) return TM_OK;
+    if (!d_pts || !d_tet) return fail(TM_ERR_ARG, "tetmesh_locate: NULL array");
+    hipError_t e = tetrt::launch_locate(m->dev, n, d_pts, d_tet, 65536,
+                                        static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "tetmesh_locate: kernel launch");
+    return TM_OK;
+}
+
+int tetmesh_tri_vertices(tm_mesh m, int64_t n, const int32_t* tri, int32_t* out) {
+    g_error.clear();
+    if (!m) return fail(TM_ERR_ARG, "tetmesh_tri_vertices: NULL mesh");
+    if (n < 0) return fail(TM_ERR_ARG, "tetmesh_tri_vertices: negative n");
+    if (n > 0 && (!tri || !out)) return fail(TM_ERR_ARG, "tetmesh_tri_vertices: NULL array");
+    for (int64_t i = 0; i < n; ++i) {
+        if (tri[i] < 0 || tri[i] >= m->ntri)
+            return fail(TM_ERR_ARG, "tetmesh_tri_vertices: triangle id %d out of range", tri[i]);
+        std::memcpy(out + 3 * i, &m->tri_verts_user[3 * (size_t)tri[i]], 3 * sizeof(int32_t));
+    }
+    return TM_OK;
+}
+
+int tetmesh_info(tm_mesh m, tm_info* out) {
+    g_error.clear();
+    if (!m || !out) return fail(TM_ERR_ARG, "tetmesh_info: NULL argument");
+    out->n_tets = m->nt;
+    out->n_points = m->np;
+    out->n_tris = m->ntri;
+    out->hot_bytes = m->hot_bytes;
+    out->cold_bytes = m->cold_bytes;
+    out->layout = m->layout;
+    out->sfc = m->sfc;
+    out->seed_grid = m->dev.G;
+    out->reserved = 0;
+    return TM_OK;
+}
+
+int tetmesh_free(tm_mesh m) {
+    g_error.clear();
+    if (!m) return TM_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (prev != m->device) (void)hipSetDevice(m->device);
+    hipError_t e = hipDeviceSynchronize();
+    release(m);
+    if (prev != m->device) (void)hipSetDevice(prev);
+    delete m;
+    if (e != hipSuccess) return hip_fail(e, "tetmesh_free: device synchronize");
+    return TM_OK;
+}
+
+int tetrt_sfc_keys(int32_t curve, int32_t bits, int64_t n, const uint32_t* xyz, uint64_t* out) {
+    g_error.clear();
+    if (bits < 1 || bits > 21) return fail(TM_ERR_ARG, "tetrt_sfc_keys: bits must be in [1, 21]");
+    if (curve != TM_SFC_HILBERT && curve != TM_SFC_MORTON)
+        return fail(TM_ERR_ARG, "tetrt_sfc_keys: unknown curve %d", curve);
+    if (n < 0 || (n > 0 && (!xyz || !out))) return fail(TM_ERR_ARG, "tetrt_sfc_keys: bad arrays");
+    const uint32_t lim = 1u << bits;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t* c = xyz + 3 * i;
+        if (c[0] >= lim || c[1] >= lim || c[2] >= lim)
+            return fail(TM_ERR_ARG, "tetrt_sfc_keys: coordinate of point %lld >= 2^bits", (long long)i);
+        out[i] = curve == TM_SFC_HILBERT ? tetrt::hilbert_key(c[0], c[1], c[2], bits)
+                                         : tetrt::morton_key(c[0], c[1], c[2], bits);
+    }
+    return TM_OK;
+}
+
+}  // extern "C"

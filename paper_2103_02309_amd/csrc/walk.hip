@@ -1,0 +1,454 @@
+// Closest-hit traversal kernels for gfx950: one lane per ray (wave64).
+//
+// Per ray (paper, Sec. "Tetrahedron Traversal"):
+//   basis     2-D basis (u, v) orthogonal to the direction, scaled so that u has
+//             a zero at the direction's smallest component and its largest
+//             components are +-1 (subsection "Point projection using
+//             specialized basis", Eq. 1-2; the divisor of v is the magnitude of
+//             its largest component, which always sits at that index).
+//   project   q(P) = (u.P - po_x, v.P - po_y) with po = (u.o, v.o) (Sec. "GPU
+//             Implementation", Eq. 4-5).  u and v are kept as full 3-vectors:
+//             their zero and +-1 entries make each fused multiply-add of the
+//             corresponding term exact, which is Eq. 3 without per-lane
+//             component selects.
+//   start     the tet containing the origin (given, or located by a straight
+//             line walk from a seed tet), whose exit face is found in 3-D once;
+//             or, for secondary rays, the tet on the far side of the start face.
+//   step      id3 = a0 ^ a1 ^ a2 ^ VX[tet]; q3 = q(P[id3]); e = Algorithm 1;
+//             next = N[tet][rank of a[e] among {a0, a1, a2, id3}] (Algorithms
+//             4-5); slot e of the kept face takes (id3, q3).
+//   stop      at a neighbour field with the top bit set: a constrained face
+//             (hit) or the boundary (miss).  The hit's t and barycentric
+//             weights are evaluated once, in float64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "device.h"
+#include "tetrt.h"
+
+namespace tetrt {
+
+namespace {
+
+constexpr uint32_t kBoundary = 0xFFFFFFFFu;
+constexpr uint32_t kIdMask = 0x7FFFFFFFu;
+
+struct Frame {
+    float ux, uy, uz;   // u (Eq. 1)
+    float vx, vy, vz;   // v (Eq. 2)
+    float pox, poy;     // projected origin (Eq. 4)
+};
+
+// 2-D determinant with both products rounded before the subtraction, so that
+// det(a, b) == -det(b, a) exactly (no fused contraction).
+__device__ __forceinline__ float det2(float ax, float ay, float bx, float by) {
+    return __fmul_rn(ax, by) - __fmul_rn(ay, bx);
+}
+
+// Eq. 1-2 for direction n (not necessarily unit).  Index names: i = smallest
+// component (lowest index of the smaller of the two non-largest ones), j = i+1,
+// k = i+2 (mod 3), and the largest component is j or k.
+__device__ __forceinline__ void specialized_basis(float nx, float ny, float nz, Frame& f) {
+    const float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
+    const int mx = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+    // the two other indices in increasing order
+    const int o1 = mx == 0 ? 1 : 0;
+    const int o2 = mx == 2 ? 1 : 2;
+    const float a1 = o1 == 0 ? ax : ay;
+    const float a2 = o2 == 1 ? ay : az;
+    const int mn = a2 < a1 ? o2 : o1;
+    // cyclic components starting at mn
+    const float ni = mn == 0 ? nx : (mn == 1 ? ny : nz);
+    const float nj = mn == 0 ? ny : (mn == 1 ? nz : nx);
+    const float nk = mn == 0 ? nz : (mn == 1 ? nx : ny);
+    const bool max_is_j = mx == (mn == 2 ? 0 : mn + 1);
+    const float nmax = max_is_j ? nj : nk;
+    // u_i = 0, u_j = n_k / n_max, u_k = -n_j / n_max (one of them is +-1 exactly)
+    const float uj = max_is_j ? nk / nmax : 1.0f;
+    const float uk = max_is_j ? -1.0f : -nj / nmax;
+    // v = (n x u) / |(n x u)_i|:  v_i = -sign(n_max), v_j, v_k = sign(n_max) n_i n_{j,k} / (n_j^2 + n_k^2)
+    const float s = nmax > 0.0f ? 1.0f : -1.0f;
+    const float w = 1.0f / (nj * nj + nk * nk);
+    const float vi = -s;
+    const float vj = s * ni * nj * w;
+    const float vk = s * ni * nk * w;
+    // scatter back to x, y, z
+    f.ux = mn == 0 ? 0.0f : (mn == 1 ? uk : uj);
+    f.uy = mn == 1 ? 0.0f : (mn == 2 ? uk : uj);
+    f.uz = mn == 2 ? 0.0f : (mn == 0 ? uk : uj);
+    f.vx = mn == 0 ? vi : (mn == 1 ? vk : vj);
+    f.vy = mn == 1 ? vi : (mn == 2 ? vk : vj);
+    f.vz = mn == 2 ? vi : (mn == 0 ? vk : vj);
+}
+
+__device__ __forceinline__ void set_origin(Frame& f, float ox, float oy, float oz) {
+    f.pox = fmaf(f.ux, ox, fmaf(f.uy, oy, f.uz * oz));
+    f.poy = fmaf(f.vx, ox, fmaf(f.vy, oy, f.vz * oz));
+}
+
+__device__ __forceinline__ void project(const Frame& f, float4 p, float& qx, float& qy) {
+    qx = fmaf(f.ux, p.x, fmaf(f.uy, p.y, fmaf(f.uz, p.z, -f.pox)));
+    qy = fmaf(f.vx, p.x, fmaf(f.vy, p.y, fmaf(f.vz, p.z, -f.poy)));
+}
+
+// parameter along the ray (in units of its direction) of P's orthogonal projection
+struct Depth {
+    float gx, gy, gz, go;
+};
+
+__device__ __forceinline__ void set_depth(Depth& g, float dx, float dy, float dz, float ox, float oy,
+                                          float oz) {
+    const float inv = 1.0f / fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    g.gx = dx * inv;
+    g.gy = dy * inv;
+    g.gz = dz * inv;
+    g.go = fmaf(g.gx, ox, fmaf(g.gy, oy, g.gz * oz));
+}
+
+__device__ __forceinline__ float depth(const Depth& g, float4 p) {
+    return fmaf(g.gx, p.x, fmaf(g.gy, p.y, fmaf(g.gz, p.z, -g.go)));
+}
+
+__device__ __forceinline__ float4 load_point(const DevMesh& m, int32_t id) {
+    return reinterpret_cast<const float4*>(m.pts)[id];
+}
+
+__device__ __forceinline__ int4 load_nb(const DevMesh& m, int32_t t) {
+    return reinterpret_cast<const int4*>(m.nb)[t];
+}
+
+__device__ __forceinline__ uint32_t pick4(int4 v, int r) {
+    return uint32_t(r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w)));
+}
+
+// Algorithm 1: which of the three kept vertices the exit face drops.
+__device__ __forceinline__ int exit_slot(float q0x, float q0y, float q1x, float q1y, float q2x,
+                                         float q2y, float q3x, float q3y) {
+    const float d0 = det2(q3x, q3y, q0x, q0y);
+    const float d1 = det2(q3x, q3y, q1x, q1y);
+    const float d2 = det2(q3x, q3y, q2x, q2y);
+    return d0 < 0.0f ? (d2 >= 0.0f ? 1 : 0) : (d1 < 0.0f ? 2 : 0);
+}
+
+// State of a walk: the kept face (ids a, 2-D points q, depths e) in
+// counter-clockwise order around the ray, and the neighbour field across it.
+struct Walk {
+    int32_t a0, a1, a2;
+    float q0x, q0y, q1x, q1y, q2x, q2y;
+    float e0, e1, e2;
+    uint32_t next;
+    int32_t cur;
+};
+
+__device__ __forceinline__ void make_ccw(Walk& w) {
+    const float o = det2(w.q1x - w.q0x, w.q1y - w.q0y, w.q2x - w.q0x, w.q2y - w.q0y);
+    if (o < 0.0f) {
+        int32_t ta = w.a1; w.a1 = w.a2; w.a2 = ta;
+        float t;
+        t = w.q1x; w.q1x = w.q2x; w.q2x = t;
+        t = w.q1y; w.q1y = w.q2y; w.q2y = t;
+        t = w.e1; w.e1 = w.e2; w.e2 = t;
+    }
+}
+
+// Exit face of tet `tet` (vertex ids v[0..3]) for the line X + s*D: the face
+// whose outward normal has n.D > 0 with the smallest crossing parameter s.
+// Fills the walk state (face ids, 2-D points in frame f, depths in g, the
+// neighbour field) and returns s (+inf when no face is front-facing).
+template <bool DEPTH>
+__device__ float start_in_tet(const DevMesh& m, int32_t tet, const int32_t v[4], float Xx, float Xy,
+                              float Xz, float Dx, float Dy, float Dz, const Frame& f, const Depth& g,
+                              Walk& w) {
+    float4 P[4];
+    float rx[4], ry[4], rz[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        P[k] = load_point(m, v[k]);
+        rx[k] = P[k].x - Xx;
+        ry[k] = P[k].y - Xy;
+        rz[k] = P[k].z - Xz;
+    }
+    float best = INFINITY;
+    int bj = -1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int A = j == 0 ? 1 : 0;
+        const int B = j <= 1 ? 2 : 1;
+        const int C = j <= 2 ? 3 : 2;
+        const float e1x = rx[B] - rx[A], e1y = ry[B] - ry[A], e1z = rz[B] - rz[A];
+        const float e2x = rx[C] - rx[A], e2y = ry[C] - ry[A], e2z = rz[C] - rz[A];
+        float nx = e1y * e2z - e1z * e2y;
+        float ny = e1z * e2x - e1x * e2z;
+        float nz = e1x * e2y - e1y * e2x;
+        const float side = nx * (rx[j] - rx[A]) + ny * (ry[j] - ry[A]) + nz * (rz[j] - rz[A]);
+        if (side > 0.0f) { nx = -nx; ny = -ny; nz = -nz; }
+        const float nd = nx * Dx + ny * Dy + nz * Dz;
+        if (nd > 0.0f) {
+            const float s = (nx * rx[A] + ny * ry[A] + nz * rz[A]) / nd;
+            if (s < best) { best = s; bj = j; }
+        }
+    }
+    if (bj < 0) return INFINITY;
+    // face ids (the three slots other than bj) and the neighbour across it;
+    // selects rather than indexing, so the arrays stay in registers
+    const float4 PA = bj == 0 ? P[1] : P[0];
+    const float4 PB = bj <= 1 ? P[2] : P[1];
+    const float4 PC = bj <= 2 ? P[3] : P[2];
+    w.a0 = bj == 0 ? v[1] : v[0];
+    w.a1 = bj <= 1 ? v[2] : v[1];
+    w.a2 = bj <= 2 ? v[3] : v[2];
+    project(f, PA, w.q0x, w.q0y);
+    project(f, PB, w.q1x, w.q1y);
+    project(f, PC, w.q2x, w.q2y);
+    if (DEPTH) {
+        w.e0 = depth(g, PA); w.e1 = depth(g, PB); w.e2 = depth(g, PC);
+    }
+    const int32_t x = bj == 0 ? v[0] : (bj == 1 ? v[1] : (bj == 2 ? v[2] : v[3]));
+    const int r = (v[0] < x) + (v[1] < x) + (v[2] < x) + (v[3] < x);
+    w.next = pick4(load_nb(m, tet), r);
+    w.cur = tet;
+    make_ccw(w);
+    return best;
+}
+
+// Point location (paper, Sec. "Locating points in a tetrahedral mesh"): the
+// traversal itself, along the segment from the centroid S of a seed tet to the
+// point; in each tet the crossing of the exit face is compared with the point
+// (parameter 1).  Constrained faces are crossed (location ignores geometry).
+// Returns the internal tet (its four ids in v) or TM_RAY_INVALID (outside) /
+// TM_RAY_STEP_CAP.
+__device__ int32_t locate_point(const DevMesh& m, float px, float py, float pz, int32_t max_steps,
+                                int32_t v[4]) {
+    int cx = int(floorf((px - m.lo[0]) * m.inv_cell[0]));
+    int cy = int(floorf((py - m.lo[1]) * m.inv_cell[1]));
+    int cz = int(floorf((pz - m.lo[2]) * m.inv_cell[2]));
+    cx = min(max(cx, 0), m.G - 1);
+    cy = min(max(cy, 0), m.G - 1);
+    cz = min(max(cz, 0), m.G - 1);
+    const int32_t seed = m.seed[(cx * m.G + cy) * m.G + cz];
+    const int4 sv = reinterpret_cast<const int4*>(m.tetv)[seed];
+    v[0] = sv.x; v[1] = sv.y; v[2] = sv.z; v[3] = sv.w;
+    float Sx = 0.f, Sy = 0.f, Sz = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float4 p = load_point(m, v[k]);
+        Sx += p.x; Sy += p.y; Sz += p.z;
+    }
+    Sx *= 0.25f; Sy *= 0.25f; Sz *= 0.25f;
+    const float Dx = px - Sx, Dy = py - Sy, Dz = pz - Sz;
+    if (Dx == 0.0f && Dy == 0.0f && Dz == 0.0f) return seed;
+    Frame f;
+    specialized_basis(Dx, Dy, Dz, f);
+    set_origin(f, Sx, Sy, Sz);
+    Depth g;
+    set_depth(g, Dx, Dy, Dz, Sx, Sy, Sz);
+    Walk w;
+    const float s0 = start_in_tet<true>(m, seed, v, Sx, Sy, Sz, Dx, Dy, Dz, f, g, w);
+    if (!(s0 < 1.0f)) return seed;
+    for (int32_t step = 0; step < max_steps; ++step) {
+        uint32_t field = w.next;
+        int32_t tet;
+        if (field == kBoundary) return TM_RAY_INVALID;
+        if (field & 0x80000000u) {
+            const uint32_t cf = field & kIdMask;
+            if (cf >= uint32_t(m.ntri)) return TM_RAY_STEP_CAP;
+            const int2 pr = reinterpret_cast<const int2*>(m.cft)[cf];
+            tet = pr.x == w.cur ? pr.y : pr.x;
+            if (tet < 0) return TM_RAY_INVALID;
+        } else {
+            tet = int32_t(field);
+        }
+        if (uint32_t(tet) >= uint32_t(m.nt)) return TM_RAY_STEP_CAP;
+        const int32_t vxv = m.vx[tet];
+        const int4 nbv = load_nb(m, tet);
+        const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ vxv;
+        if (uint32_t(id3) >= uint32_t(m.np)) return TM_RAY_STEP_CAP;
+        const float4 P = load_point(m, id3);
+        float q3x, q3y;
+        project(f, P, q3x, q3y);
+        const float e3 = depth(g, P);
+        const int e = exit_slot(w.q0x, w.q0y, w.q1x, w.q1y, w.q2x, w.q2y, q3x, q3y);
+        const int32_t x = e == 0 ? w.a0 : (e == 1 ? w.a1 : w.a2);
+        const int r = (w.a0 < x) + (w.a1 < x) + (w.a2 < x) + (id3 < x);
+        w.next = pick4(nbv, r);
+        w.cur = tet;
+        if (e == 0) { w.a0 = id3; w.q0x = q3x; w.q0y = q3y; w.e0 = e3; }
+        else if (e == 1) { w.a1 = id3; w.q1x = q3x; w.q1y = q3y; w.e1 = e3; }
+        else { w.a2 = id3; w.q2x = q3x; w.q2y = q3y; w.e2 = e3; }
+        // the segment leaves this tet through the new face at the depth of the
+        // 2-D origin's barycentric combination; at or beyond 1 the point is inside
+        const float l0 = det2(w.q1x, w.q1y, w.q2x, w.q2y);
+        const float l1 = det2(w.q2x, w.q2y, w.q0x, w.q0y);
+        const float l2 = det2(w.q0x, w.q0y, w.q1x, w.q1y);
+        if (l0 * (w.e0 - 1.0f) + l1 * (w.e1 - 1.0f) + l2 * (w.e2 - 1.0f) >= 0.0f) {
+            v[0] = w.a0; v[1] = w.a1; v[2] = w.a2; v[3] = x;
+            return tet;
+        }
+    }
+    return TM_RAY_STEP_CAP;
+}
+
+__device__ __forceinline__ void write_result(const RayArgs& r, int64_t i, int32_t code, float t,
+                                             float b1, float b2, int32_t front, int32_t back,
+                                             int32_t steps) {
+    r.tri[i] = code;
+    r.t[i] = t;
+    reinterpret_cast<float2*>(r.bary)[i] = make_float2(b1, b2);
+    if (r.hit_tets) reinterpret_cast<int2*>(r.hit_tets)[i] = make_int2(front, back);
+    if (r.steps) r.steps[i] = steps;
+}
+
+template <bool TMAX>
+__global__ void __launch_bounds__(256) k_trace(DevMesh m, RayArgs r) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= r.n) return;
+    const float NaN = __int_as_float(0x7fc00000);
+    const float ox = r.orig[3 * i], oy = r.orig[3 * i + 1], oz = r.orig[3 * i + 2];
+    const float dx = r.dir[3 * i], dy = r.dir[3 * i + 1], dz = r.dir[3 * i + 2];
+    const float tmax = TMAX ? r.tmax[i] : INFINITY;
+    const float dd = dx * dx + dy * dy + dz * dz;
+    if (!(dd > 0.0f) || !isfinite(dd) || !isfinite(ox + oy + oz) || isnan(tmax)) {
+        write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0);
+        return;
+    }
+    const int32_t sf = r.start_face ? r.start_face[i] : -1;
+    Walk w;
+    Frame f;
+    Depth g;
+    if (sf >= 0) {
+        // secondary ray: start in the tet on the side of the face that dir points into
+        if (sf >= m.ntri) { write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0); return; }
+        const int4 fv = reinterpret_cast<const int4*>(m.cfv)[sf];
+        const int2 ft = reinterpret_cast<const int2*>(m.cft)[sf];
+        const float4 PA = load_point(m, fv.x), PB = load_point(m, fv.y), PC = load_point(m, fv.z);
+        const float e1x = PB.x - PA.x, e1y = PB.y - PA.y, e1z = PB.z - PA.z;
+        const float e2x = PC.x - PA.x, e2y = PC.y - PA.y, e2z = PC.z - PA.z;
+        const float nd = (e1y * e2z - e1z * e2y) * dx + (e1z * e2x - e1x * e2z) * dy +
+                         (e1x * e2y - e1y * e2x) * dz;
+        if (nd == 0.0f) { write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0); return; }
+        const int32_t start = nd > 0.0f ? ft.x : ft.y;
+        if (start < 0) { write_result(r, i, TM_RAY_MISS, NaN, NaN, NaN, -1, -1, 0); return; }
+        specialized_basis(dx, dy, dz, f);
+        set_origin(f, ox, oy, oz);
+        if (TMAX) set_depth(g, dx, dy, dz, ox, oy, oz);
+        w.a0 = fv.x; w.a1 = fv.y; w.a2 = fv.z;
+        project(f, PA, w.q0x, w.q0y);
+        project(f, PB, w.q1x, w.q1y);
+        project(f, PC, w.q2x, w.q2y);
+        if (TMAX) { w.e0 = depth(g, PA); w.e1 = depth(g, PB); w.e2 = depth(g, PC); }
+        make_ccw(w);
+        w.next = uint32_t(start);
+        w.cur = -1;
+    } else {
+        int32_t v[4];
+        int32_t tet;
+        const int32_t st = r.start_tet ? r.start_tet[i] : -1;
+        if (st >= 0) {
+            if (st >= m.nt) { write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0); return; }
+            tet = m.t_old2new[st];
+            const int4 sv = reinterpret_cast<const int4*>(m.tetv)[tet];
+            v[0] = sv.x; v[1] = sv.y; v[2] = sv.z; v[3] = sv.w;
+        } else {
+            tet = locate_point(m, ox, oy, oz, r.max_steps, v);
+            if (tet < 0) { write_result(r, i, tet, NaN, NaN, NaN, -1, -1, 0); return; }
+        }
+        specialized_basis(dx, dy, dz, f);
+        set_origin(f, ox, oy, oz);
+        if (TMAX) set_depth(g, dx, dy, dz, ox, oy, oz);
+        const float s = start_in_tet<TMAX>(m, tet, v, ox, oy, oz, dx, dy, dz, f, g, w);
+        if (!(s < INFINITY)) { write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0); return; }
+    }
+
+    // ---- the walk ------------------------------------------------------------
+    int32_t steps = 0;
+    int32_t code = 0;
+    for (;;) {
+        if (w.next & 0x80000000u) break;  // constrained face or boundary
+        if (TMAX && fminf(w.e0, fminf(w.e1, w.e2)) > tmax) { code = TM_RAY_MISS; break; }
+        if (steps >= r.max_steps || w.next >= uint32_t(m.nt)) { code = TM_RAY_STEP_CAP; break; }
+        ++steps;
+        const int32_t tet = int32_t(w.next);
+        const int32_t vxv = m.vx[tet];
+        const int4 nbv = load_nb(m, tet);
+        const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ vxv;
+        if (uint32_t(id3) >= uint32_t(m.np)) { code = TM_RAY_STEP_CAP; break; }
+        const float4 P = load_point(m, id3);
+        float q3x, q3y;
+        project(f, P, q3x, q3y);
+        const int e = exit_slot(w.q0x, w.q0y, w.q1x, w.q1y, w.q2x, w.q2y, q3x, q3y);
+        const int32_t x = e == 0 ? w.a0 : (e == 1 ? w.a1 : w.a2);
+        const int rk = (w.a0 < x) + (w.a1 < x) + (w.a2 < x) + (id3 < x);
+        w.next = pick4(nbv, rk);
+        w.cur = tet;
+        float e3 = 0.0f;
+        if (TMAX) e3 = depth(g, P);
+        if (e == 0) { w.a0 = id3; w.q0x = q3x; w.q0y = q3y; if (TMAX) w.e0 = e3; }
+        else if (e == 1) { w.a1 = id3; w.q1x = q3x; w.q1y = q3y; if (TMAX) w.e1 = e3; }
+        else { w.a2 = id3; w.q2x = q3x; w.q2y = q3y; if (TMAX) w.e2 = e3; }
+    }
+    if (code != 0) { write_result(r, i, code, NaN, NaN, NaN, -1, -1, steps); return; }
+    if (w.next == kBoundary) { write_result(r, i, TM_RAY_MISS, NaN, NaN, NaN, -1, -1, steps); return; }
+
+    // ---- the hit: t and barycentric weights in float64 (Moller-Trumbore) -----
+    const uint32_t cf = w.next & kIdMask;
+    if (cf >= uint32_t(m.ntri)) { write_result(r, i, TM_RAY_STEP_CAP, NaN, NaN, NaN, -1, -1, steps); return; }
+    const int4 fv = reinterpret_cast<const int4*>(m.cfv)[cf];   // ascending caller ids
+    const float4 A = load_point(m, fv.x), B = load_point(m, fv.y), C = load_point(m, fv.z);
+    const double e1x = double(B.x) - A.x, e1y = double(B.y) - A.y, e1z = double(B.z) - A.z;
+    const double e2x = double(C.x) - A.x, e2y = double(C.y) - A.y, e2z = double(C.z) - A.z;
+    const double sx = double(ox) - A.x, sy = double(oy) - A.y, sz = double(oz) - A.z;
+    const double Dx = dx, Dy = dy, Dz = dz;
+    const double px = Dy * e2z - Dz * e2y, py = Dz * e2x - Dx * e2z, pz = Dx * e2y - Dy * e2x;
+    const double det = e1x * px + e1y * py + e1z * pz;
+    const double inv = 1.0 / det;
+    const double bu = (sx * px + sy * py + sz * pz) * inv;
+    const double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    const double bv = (Dx * qx + Dy * qy + Dz * qz) * inv;
+    const double th = (e2x * qx + e2y * qy + e2z * qz) * inv;
+    if (TMAX && th > double(tmax)) { write_result(r, i, TM_RAY_MISS, NaN, NaN, NaN, -1, -1, steps); return; }
+    int32_t front = -1, back = -1;
+    if (r.hit_tets) {
+        const int2 ft = reinterpret_cast<const int2*>(m.cft)[cf];
+        const int32_t other = ft.x == w.cur ? ft.y : ft.x;
+        front = m.t_new2old[w.cur];
+        back = other >= 0 ? m.t_new2old[other] : -1;
+    }
+    write_result(r, i, int32_t(cf), float(th), float(bu), float(bv), front, back, steps);
+}
+
+__global__ void __launch_bounds__(256) k_locate(DevMesh m, int64_t n, const float* pts, int32_t* out,
+                                                int32_t max_steps) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float px = pts[3 * i], py = pts[3 * i + 1], pz = pts[3 * i + 2];
+    if (!isfinite(px + py + pz)) { out[i] = -1; return; }
+    int32_t v[4];
+    const int32_t t = locate_point(m, px, py, pz, max_steps, v);
+    out[i] = t >= 0 ? m.t_new2old[t] : (t == TM_RAY_STEP_CAP ? -2 : -1);
+}
+
+}  // namespace
+
+hipError_t launch_trace(const DevMesh& m, const RayArgs& r, int block, hipStream_t s) {
+    if (r.n <= 0) return hipSuccess;
+    if (block != 64 && block != 128 && block != 256) block = 256;
+    const int64_t grid = (r.n + block - 1) / block;
+    if (r.tmax)
+        hipLaunchKernelGGL(k_trace<true>, dim3(unsigned(grid)), dim3(block), 0, s, m, r);
+    else
+        hipLaunchKernelGGL(k_trace<false>, dim3(unsigned(grid)), dim3(block), 0, s, m, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_locate(const DevMesh& m, int64_t n, const float* pts, int32_t* out,
+                         int32_t max_steps, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int block = 256;
+    const int64_t grid = (n + block - 1) / block;
+    hipLaunchKernelGGL(k_locate, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
+    return hipGetLastError();
+}
+
+}  // namespace tetrt

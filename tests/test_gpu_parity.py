@@ -1,0 +1,181 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle on the same
+seeded inputs."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from oracle.compare import compare
+from synth import (config_mesh, kuhn_mesh, pinhole_rays, ao_rays, tri_geometry,
+                   random_interior_rays)
+from synth.kuhn import random_spheres
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _host(res):
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in res.items()}
+
+
+@pytest.fixture(scope="module")
+def tetrt():
+    import paper_2103_02309_amd as tetrt
+    return tetrt
+
+
+@pytest.fixture(scope="module")
+def tiny(tetrt, tiny_mesh, tiny_oracle):
+    mesh = tetrt.upload(tiny_mesh.points, tiny_mesh.tets, tiny_mesh.nbrs, tiny_mesh.cflag)
+    yield tiny_mesh, tiny_oracle, mesh
+    mesh.free()
+
+
+def _ao_from(m, om, o, d, ref, k=8, seed=3, tmax=0.1):
+    hit = ref["tri"] >= 0
+    hp = o[hit].astype(np.float64) + ref["t"][hit, None] * d[hit].astype(np.float64)
+    nrm, _ = tri_geometry(m.points, om.tri_verts[ref["tri"][hit]])
+    ao, ad, atm, parent = ao_rays(hp, nrm, d[hit], k=k, seed=seed, tmax=tmax)
+    return ao, ad, atm, ref["tri"][hit][parent].astype(np.int32)
+
+
+def test_tiny_primary(tiny):
+    m, om, mesh = tiny
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 64, 64, 60.0)
+    got = _host(mesh.trace(_dev(o), _dev(d), want_tets=True, want_steps=True))
+    ref = om.trace(o, d)
+    rep = compare(m.points, om.tri_verts, o, d, ref, got)
+    assert rep["ok"], rep
+    same = got["tri"] == ref["tri"]
+    assert np.array_equal(got["hit_tets"][same], ref["tets"][same])
+    assert (got["steps"] == ref["steps"]).mean() > 0.999
+
+
+def test_tiny_ao(tiny):
+    m, om, mesh = tiny
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 64, 64, 60.0)
+    ref0 = om.trace(o, d)
+    ao, ad, atm, sf = _ao_from(m, om, o, d, ref0)
+    got = _host(mesh.trace(_dev(ao), _dev(ad), tmax=_dev(atm), start_face=_dev(sf), want_tets=True))
+    ref = om.trace(ao, ad, atm, start_face=sf)
+    rep = compare(m.points, om.tri_verts, ao, ad, ref, got, tmax=atm)
+    assert rep["ok"], rep
+    same = (got["tri"] == ref["tri"]) & (ref["tri"] >= 0)
+    assert np.array_equal(got["hit_tets"][same], ref["tets"][same])
+
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (8, 2), (13, 3)])
+def test_random_rays_small_meshes(tetrt, n, seed):
+    m = kuhn_mesh(n, jitter=0.1, seed=seed, spheres=random_spheres(4, seed=seed, r_lo=0.1, r_hi=0.3))
+    om = oracle.OracleMesh.from_kuhn(m)
+    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag)
+    o, d = random_interior_rays(20000, seed)
+    tm = np.random.default_rng(seed).uniform(0.05, 1.5, 20000).astype(np.float32)
+    tm[::4] = np.inf
+    got = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm)))
+    ref = om.trace(o, d, tm)
+    rep = compare(m.points, om.tri_verts, o, d, ref, got, tmax=tm)
+    assert rep["ok"], rep
+    # the same rays without tmax
+    got = _host(mesh.trace(_dev(o), _dev(d)))
+    ref = om.trace(o, d)
+    rep = compare(m.points, om.tri_verts, o, d, ref, got)
+    assert rep["ok"], rep
+    mesh.free()
+
+
+def test_start_tet_matches_location(tiny):
+    m, om, mesh = tiny
+    o, d = random_interior_rays(5000, 17)
+    st = om.locate(o)
+    a = _host(mesh.trace(_dev(o), _dev(d)))
+    b = _host(mesh.trace(_dev(o), _dev(d), start_tet=_dev(st)))
+    assert (a["tri"] == b["tri"]).mean() > 0.999
+    ref = om.trace(o, d, start_tet=st)
+    assert compare(m.points, om.tri_verts, o, d, ref, b)["ok"]
+
+
+def test_locate_contains_points(tiny):
+    m, om, mesh = tiny
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.0, 1.0, size=(20000, 3)).astype(np.float32)
+    t = mesh.locate(_dev(x)).cpu().numpy()
+    assert np.all(t >= 0)
+    P = m.points.astype(np.float64)
+    V = P[m.tets[t]]
+    X = x.astype(np.float64)
+    worst = np.zeros(len(x))
+    for j in range(4):
+        f = [s for s in range(4) if s != j]
+        A, B, Cc, W = V[:, f[0]], V[:, f[1]], V[:, f[2]], V[:, j]
+        nrm = np.cross(B - A, Cc - A)
+        nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+        sx = np.einsum("ij,ij->i", nrm, X - A) * np.sign(np.einsum("ij,ij->i", nrm, W - A))
+        worst = np.minimum(worst, sx)
+    # inside up to float32 rounding of the walk (distance below 1e-6 of the extent)
+    assert worst.min() > -1e-6
+    ref = om.locate(x)
+    assert (ref == t).mean() > 0.999
+    out = mesh.locate(_dev(np.array([[1.5, 0.5, 0.5], [0.5, -0.2, 0.5]], np.float32))).cpu().numpy()
+    assert out.tolist() == [-1, -1]
+
+
+def test_invalid_inputs(tiny, tetrt):
+    m, om, mesh = tiny
+    o = np.array([[0.5, 0.5, 0.05]] * 4 + [[2.0, 0.5, 0.5]], np.float32)
+    d = np.array([[0, 0, 0], [np.nan, 0, 1], [0, 0, np.inf], [0, 0, 1], [0, 0, 1]], np.float32)
+    got = _host(mesh.trace(_dev(o), _dev(d)))
+    assert got["tri"].tolist()[:3] == [tetrt.RAY_INVALID] * 3
+    assert got["tri"][3] >= 0
+    assert got["tri"][4] == tetrt.RAY_INVALID
+    assert np.isnan(got["t"][[0, 1, 2, 4]]).all()
+    sf = np.array([-1, -1, -1, om.ntri, -1], np.int32)
+    got = _host(mesh.trace(_dev(o), _dev(d), start_face=_dev(sf)))
+    assert got["tri"][3] == tetrt.RAY_INVALID
+    st = np.array([-1, -1, -1, m.n_tets, -1], np.int32)
+    got = _host(mesh.trace(_dev(o), _dev(d), start_tet=_dev(st)))
+    assert got["tri"][3] == tetrt.RAY_INVALID
+    # empty batch is a no-op
+    e = torch.empty((0, 3), dtype=torch.float32, device="cuda:0")
+    mesh.trace(e, e)
+
+
+def test_sfc_orders_agree(tetrt, tiny_mesh, tiny_oracle):
+    m = tiny_mesh
+    o, d = random_interior_rays(20000, 23)
+    outs = {}
+    for sfc in ("hilbert", "morton", "none"):
+        mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, sfc=sfc)
+        outs[sfc] = _host(mesh.trace(_dev(o), _dev(d)))
+        mesh.free()
+    for sfc in ("morton", "none"):
+        same = outs[sfc]["tri"] == outs["hilbert"]["tri"]
+        assert same.mean() > 0.9999
+        hit = same & (outs[sfc]["tri"] >= 0)
+        # t and bary come from the same triangle and ray in float64: bit-identical
+        assert np.array_equal(outs[sfc]["t"][hit], outs["hilbert"]["t"][hit])
+
+
+def test_step_cap_reports_code(tiny, tetrt):
+    m, om, mesh = tiny
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 8, 8, 60.0)
+    got = _host(mesh.trace(_dev(o), _dev(d), max_steps=1))
+    ref = om.trace(o, d)
+    # rays that need more than one step stop with the step-cap code
+    assert np.all(got["tri"][ref["steps"] > 1] == tetrt.RAY_STEP_CAP)
+    ok = ref["steps"] <= 1
+    assert np.array_equal(got["tri"][ok], ref["tri"][ok])
+
+
+def test_repeat_calls_identical(tiny):
+    m, om, mesh = tiny
+    o, d = random_interior_rays(50000, 29)
+    a = _host(mesh.trace(_dev(o), _dev(d)))
+    b = _host(mesh.trace(_dev(o), _dev(d), block=64))
+    assert np.array_equal(a["tri"], b["tri"])
+    assert np.array_equal(a["t"], b["t"], equal_nan=True)
