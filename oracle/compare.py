@@ -39,6 +39,44 @@ def _plane_point(P, tri_verts, tri, o, d):
     return o + t[:, None] * d
 
 
+def _line_seg_dist(o, u, a, b):
+    """Distance between the lines o + s*u (u unit, s free) and segments ab."""
+    e = b - a
+    w0 = o - a
+    bb = np.einsum("ij,ij->i", u, e)
+    cc = np.einsum("ij,ij->i", e, e)
+    dd = np.einsum("ij,ij->i", u, w0)
+    ee = np.einsum("ij,ij->i", e, w0)
+    den = cc - bb * bb
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = np.where(den > 1e-300, (ee - bb * dd) / den, 0.0)
+    v = np.clip(v, 0.0, 1.0)
+    s = bb * v - dd
+    return np.linalg.norm(w0 + s[:, None] * u - v[:, None] * e, axis=1)
+
+
+def ray_triangle_gap(points, tri_verts, tri, orig, dirs):
+    """How far the line of each ray passes from its reported triangle: 0 when it
+    crosses the triangle, else the distance to the nearest edge (float64)."""
+    P = np.asarray(points, dtype=np.float64)
+    tv = np.asarray(tri_verts)[tri]
+    A, B, Cc = P[tv[:, 0]], P[tv[:, 1]], P[tv[:, 2]]
+    o = np.asarray(orig, dtype=np.float64).reshape(-1, 3)
+    d = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+    u = d / np.linalg.norm(d, axis=1, keepdims=True)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        # inside test of the plane point
+        n = np.cross(B - A, Cc - A)
+        t = np.einsum("ij,ij->i", n, A - o) / np.einsum("ij,ij->i", n, u)
+        h = o + t[:, None] * u
+        inside = np.ones(len(o), dtype=bool)
+        for X, Y in ((A, B), (B, Cc), (Cc, A)):
+            inside &= np.einsum("ij,ij->i", np.cross(Y - X, h - X), n) >= 0
+        gap = np.minimum(np.minimum(_line_seg_dist(o, u, A, B), _line_seg_dist(o, u, B, Cc)),
+                         _line_seg_dist(o, u, Cc, A))
+    return np.where(inside & np.isfinite(t), 0.0, gap)
+
+
 def compare(points, tri_verts, orig, dirs, ref, got, tmax=None, extent=1.0, edge_tol=1e-6,
             t_rtol=1e-5, bary_tol=1e-4, tmax_rtol=1e-6, min_identical=0.9999):
     """Compare ``got`` (numpy dict: tri, t, bary) with oracle results ``ref``.
