@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=8, help="pixel tile edge for ray order (1 = row-major)")
     ap.add_argument("--sfc", default="hilbert", choices=["hilbert", "morton", "none"])
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 one lane per ray, 2 persistent")
+    ap.add_argument("--refill", type=int, default=0, help="persistent refill threshold (0 = default)")
     ap.add_argument("--ao", type=int, default=8, help="AO rays per primary hit")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-stride", type=int, default=4,
@@ -126,9 +128,11 @@ def main():
              "t": torch.empty(n_a, dtype=torch.float32, device=dev),
              "bary": torch.empty((n_a, 2), dtype=torch.float32, device=dev)}
 
+    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill)
+
     def step():
-        mesh.trace_into(out_p, po, pd, block=args.block)
-        mesh.trace_into(out_a, ao_t, ad_t, tmax=atm_t, start_face=sf_t, block=args.block)
+        mesh.trace_into(out_p, po, pd, **kw)
+        mesh.trace_into(out_a, ao_t, ad_t, tmax=atm_t, start_face=sf_t, **kw)
 
     for _ in range(args.warmup):
         step()
@@ -147,9 +151,9 @@ def main():
     t_wall = time.perf_counter()
     for k in range(K):
         ev[k][0].record()
-        mesh.trace_into(out_p, po, pd, block=args.block)
+        mesh.trace_into(out_p, po, pd, **kw)
         ev[k][1].record()
-        mesh.trace_into(out_a, ao_t, ad_t, tmax=atm_t, start_face=sf_t, block=args.block)
+        mesh.trace_into(out_a, ao_t, ad_t, tmax=atm_t, start_face=sf_t, **kw)
         ev[k][2].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
@@ -187,6 +191,7 @@ def main():
             "primary_rays": n_p, "ao_rays": n_a, "ray_order": "8x8 tiles" if args.tile == 8 else
             ("row-major" if args.tile <= 1 else "%dx%d tiles" % (args.tile, args.tile)),
             "layout": "tet20", "sfc": args.sfc, "block": args.block,
+            "kernel": {0: "auto", 1: "one lane per ray", 2: "persistent lanes"}[args.kernel],
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -93,8 +93,12 @@ typedef struct {
 typedef struct {
     int32_t max_steps;   /* walk step cap per ray (tets entered); 0 = 65536 */
     int32_t block;       /* threads per block: 64, 128 or 256 (0 = 256) */
-    int32_t reserved0;
-    int32_t reserved1;
+    int32_t kernel;      /* 0 = automatic, 1 = one lane per ray, 2 = persistent lanes that
+                            take further rays as theirs finish */
+    int32_t refill;      /* persistent lanes: finished lanes per wavefront that trigger a
+                            refill, 1..64 (0 = 16) */
+    int32_t grid_cap;    /* persistent lanes: at most this many blocks (0 = enough blocks
+                            to fill every compute unit) */
 } tm_trace_opts;
 
 /*
@@ -120,8 +124,9 @@ typedef struct {
  *                                      set on both sides of an interior face
  *   opts     host, nullable
  *   out      host; receives the handle (owns all device memory until tetmesh_free)
- * Limits: 1 <= n_tets < 2^31 - 1, 4 <= n_points < 2^31, fewer than 2^31 - 1
- * constrained triangles.  Inputs are copied; the caller may free them on return.
+ * Limits: 1 <= n_tets <= 214,748,364 (20-byte records addressed by 32-bit byte
+ * offsets), 4 <= n_points <= 268,435,455, fewer than 2^31 - 1 constrained
+ * triangles.  Inputs are copied; the caller may free them on return.
  * Errors: TM_ERR_ARG, TM_ERR_MESH (with validate = 1: vertex id out of range,
  * repeated vertex, zero volume, neighbour link not mutual, neighbours not
  * sharing the face, flag set on one side only -- the first offending tet is

@@ -15,6 +15,7 @@
 struct tm_mesh_s {
     tetrt::DevMesh dev{};
     int device = 0;
+    int cus = 0;
     int64_t np = 0, nt = 0, ntri = 0;
     int32_t layout = 0, sfc = 0;
     int64_t hot_bytes = 0, cold_bytes = 0;
@@ -84,6 +85,10 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     if (n_points < 4 || n_points >= int64_t(0x80000000LL))
         return fail(TM_ERR_ARG, "tetmesh_upload: n_points = %lld out of range [4, 2^31)",
                     (long long)n_points);
+    // the kernels address records and points with 32-bit byte offsets
+    if (n_tets * 20 > int64_t(0xFFFFFFFFLL) || n_points * 16 > int64_t(0xFFFFFFFFLL))
+        return fail(TM_ERR_ARG, "tetmesh_upload: mesh too large (at most %lld tets and %lld points)",
+                    (long long)(0xFFFFFFFFLL / 20), (long long)(0xFFFFFFFFLL / 16));
     tm_upload_opts o = {TM_LAYOUT_TET20, TM_SFC_HILBERT, 1, 0};
     if (opts) o = *opts;
     if (o.layout != TM_LAYOUT_TET20)
@@ -106,6 +111,11 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     tm_mesh_s* m = new (std::nothrow) tm_mesh_s();
     if (!m) return fail(TM_ERR_OOM, "tetmesh_upload: host allocation failed");
     (void)hipGetDevice(&m->device);
+    if (hipDeviceGetAttribute(&m->cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
+        m->cus <= 0) {
+        (void)hipGetLastError();
+        m->cus = 256;
+    }
     m->np = pm.np;
     m->nt = pm.nt;
     m->ntri = pm.ntri;
@@ -113,7 +123,7 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     m->sfc = pm.sfc;
     int64_t hot = 0, cold = 0;
     tetrt::DevMesh& d = m->dev;
-    if ((rc = upload_array(m, pm.vx, &d.vx, &hot)) || (rc = upload_array(m, pm.nb, &d.nb, &hot)) ||
+    if ((rc = upload_array(m, pm.rec, &d.rec, &hot)) ||
         (rc = upload_array(m, pm.pts4, &d.pts, &hot)) ||
         (rc = upload_array(m, pm.tetv, &d.tetv, &cold)) ||
         (rc = upload_array(m, pm.cfv, &d.cfv, &cold)) ||
@@ -154,11 +164,14 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
         return fail(TM_ERR_ARG, "trace_closest: NULL required array");
     if ((reinterpret_cast<uintptr_t>(d_bary) & 7) || (reinterpret_cast<uintptr_t>(d_hit_tets) & 7))
         return fail(TM_ERR_ARG, "trace_closest: bary / hit_tets must be 8-byte aligned");
-    tm_trace_opts o = {0, 0, 0, 0};
+    tm_trace_opts o = {0, 0, 0, 0, 0};
     if (opts) o = *opts;
     if (o.max_steps < 0) return fail(TM_ERR_ARG, "trace_closest: negative max_steps");
     if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
         return fail(TM_ERR_ARG, "trace_closest: block must be 64, 128 or 256");
+    if (o.kernel < 0 || o.kernel > 2) return fail(TM_ERR_ARG, "trace_closest: kernel must be 0, 1 or 2");
+    if (o.refill < 0 || o.refill > 64) return fail(TM_ERR_ARG, "trace_closest: refill must be in [0, 64]");
+    if (o.grid_cap < 0) return fail(TM_ERR_ARG, "trace_closest: negative grid_cap");
     tetrt::RayArgs r;
     r.orig = d_orig;
     r.dir = d_dir;
@@ -172,8 +185,16 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     r.steps = d_steps;
     r.n = n_rays;
     r.max_steps = o.max_steps > 0 ? o.max_steps : 65536;
-    hipError_t e = tetrt::launch_trace(m->dev, r, o.block ? o.block : 256,
-                                       static_cast<hipStream_t>(hip_stream));
+    tetrt::LaunchCfg c;
+    c.block = o.block ? o.block : 256;
+    c.cus = m->cus;
+    c.waves_per_simd = 8;
+    c.refill = o.refill ? o.refill : 16;
+    c.grid_cap = o.grid_cap;
+    // persistent lanes pay off once every lane gets several rays
+    const int64_t lanes = int64_t(c.cus) * 4 * 64 * c.waves_per_simd;
+    c.kernel = o.kernel ? o.kernel : (n_rays >= 4 * lanes ? 2 : 1);
+    hipError_t e = tetrt::launch_trace(m->dev, r, c, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "trace_closest: kernel launch");
     return TM_OK;
 }

@@ -1,5 +1,6 @@
 // Device-side view of an uploaded mesh and the kernel launchers.
 #pragma once
+#include <algorithm>
 #include <cstdint>
 
 #include <hip/hip_runtime_api.h>
@@ -10,8 +11,7 @@ namespace tetrt {
 // kernels by value.  Vector-typed arrays are stored as their scalar base type
 // and reinterpreted in the kernels (int4 / float4 / int2, 16- or 8-byte aligned).
 struct DevMesh {
-    const int32_t* vx;        // [nt]      Tet20 xor field
-    const int32_t* nb;        // [nt*4]    Tet20 neighbour fields (int4 per tet)
+    const int32_t* rec;       // [nt*5]    Tet20 records: xor field, 4 neighbour fields
     const float* pts;         // [np*4]    float4 per point
     const int32_t* tetv;      // [nt*4]    ascending vertex ids (int4 per tet)
     const int32_t* cfv;       // [ntri*4]  constrained-face vertices (int4)
@@ -42,7 +42,16 @@ struct RayArgs {
     int32_t max_steps;
 };
 
-hipError_t launch_trace(const DevMesh& m, const RayArgs& r, int block, hipStream_t s);
+struct LaunchCfg {
+    int32_t block;          // threads per block (64, 128 or 256)
+    int32_t kernel;         // 1 = one lane per ray, 2 = persistent lanes
+    int32_t refill;         // persistent: finished lanes per wave that trigger a refill
+    int32_t waves_per_simd; // persistent: resident waves per SIMD to launch for
+    int32_t cus;            // compute units of the device
+    int32_t grid_cap;       // persistent: at most this many blocks (0 = no cap)
+};
+
+hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s);
 hipError_t launch_locate(const DevMesh& m, int64_t n, const float* pts, int32_t* out,
                          int32_t max_steps, hipStream_t s);
 

@@ -321,8 +321,7 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
     }
 
     // ---- Tet20 records ---------------------------------------------------------
-    M.vx.resize(nt);
-    M.nb.resize(size_t(4 * nt));
+    M.rec.resize(size_t(5 * nt));
     M.tetv.resize(size_t(4 * nt));
     parallel_for(nt, [&](int64_t b, int64_t e) {
         for (int64_t tn = b; tn < e; ++tn) {
@@ -337,7 +336,7 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
                     std::swap(v[c], v[c - 1]);
                     std::swap(slot[c], slot[c - 1]);
                 }
-            M.vx[tn] = v[0] ^ v[1] ^ v[2] ^ v[3];
+            M.rec[5 * tn] = v[0] ^ v[1] ^ v[2] ^ v[3];
             for (int r = 0; r < 4; ++r) {
                 int64_t f = 4 * t + slot[r];
                 uint32_t field;
@@ -347,7 +346,7 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
                     field = kBoundaryField;
                 else
                     field = uint32_t(M.t_old2new[nbrs[f]]);
-                M.nb[4 * tn + r] = int32_t(field);
+                M.rec[5 * tn + 1 + r] = int32_t(field);
                 M.tetv[4 * tn + r] = v[r];
             }
         }

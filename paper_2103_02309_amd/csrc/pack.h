@@ -17,8 +17,8 @@ struct PackedMesh {
     int64_t np = 0, nt = 0, ntri = 0;
     int32_t layout = 0, sfc = 0;
     std::vector<float> pts4;             // [np*4]   x, y, z, 0 in internal point order
-    std::vector<int32_t> vx;             // [nt]     xor of the four internal vertex ids
-    std::vector<int32_t> nb;             // [nt*4]   neighbour fields, by ascending vertex id
+    std::vector<int32_t> rec;            // [nt*5]   Tet20: xor of the four internal vertex ids,
+                                         //          then the neighbour fields by ascending vertex id
     std::vector<int32_t> tetv;           // [nt*4]   internal vertex ids, ascending (cold)
     std::vector<int32_t> cfv;            // [ntri*4] internal ids of the triangle's vertices in
                                          //          ascending caller-id order, then 0

@@ -20,6 +20,13 @@
 //   stop      at a neighbour field with the top bit set: a constrained face
 //             (hit) or the boundary (miss).  The hit's t and barycentric
 //             weights are evaluated once, in float64.
+//
+// Memory: a tet record is 20 packed bytes {VX, N0, N1, N2, N3} (the paper's
+// Tet20), read as one 16-byte and one 4-byte buffer load issued together at the
+// top of a step; the point is one 16-byte load.  A step is therefore two
+// dependent round trips (record, then point).  Buffer loads return zero beyond
+// the array instead of faulting, and the step is branch-free: the loop test is
+// its only branch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,7 +40,46 @@ namespace tetrt {
 namespace {
 
 constexpr uint32_t kBoundary = 0xFFFFFFFFu;
+constexpr uint32_t kAbort = 0xFFFFFFFEu;   // internal: the walk met an inconsistent record
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
+constexpr uint32_t kRecBytes = 20;         // Tet20 record
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+// gfx9-family buffer descriptor, raw (stride 0) addressing, bounds = byte size
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint64_t bytes) {
+    const uint32_t n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(n), 0x00020000);
+}
+
+struct Mem {
+    rsrc_t rec;
+    rsrc_t pts;
+};
+
+__device__ __forceinline__ Mem make_mem(const DevMesh& m) {
+    Mem M;
+    M.rec = make_rsrc(m.rec, uint64_t(m.nt) * kRecBytes);
+    M.pts = make_rsrc(m.pts, uint64_t(m.np) * 16u);
+    return M;
+}
+
+struct Rec {
+    int32_t vx;
+    uint32_t n0, n1, n2, n3;
+};
+
+__device__ __forceinline__ Rec load_rec(const Mem& M, uint32_t tet) {
+    const uint32_t off = tet * kRecBytes;
+    const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, off, 0, 0);
+    const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(M.rec, off + 16u, 0, 0);
+    return Rec{int32_t(a[0]), a[1], a[2], a[3], b};
+}
+
+__device__ __forceinline__ float4 load_pt(const Mem& M, uint32_t id) {
+    const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.pts, id * 16u, 0, 0);
+    return make_float4(__uint_as_float(a[0]), __uint_as_float(a[1]), __uint_as_float(a[2]), 0.0f);
+}
 
 struct Frame {
     float ux, uy, uz;   // u (Eq. 1)
@@ -53,14 +99,12 @@ __device__ __forceinline__ float det2(float ax, float ay, float bx, float by) {
 __device__ __forceinline__ void specialized_basis(float nx, float ny, float nz, Frame& f) {
     const float ax = fabsf(nx), ay = fabsf(ny), az = fabsf(nz);
     const int mx = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
-    // the two other indices in increasing order
-    const int o1 = mx == 0 ? 1 : 0;
+    const int o1 = mx == 0 ? 1 : 0;    // the two other indices, increasing
     const int o2 = mx == 2 ? 1 : 2;
     const float a1 = o1 == 0 ? ax : ay;
     const float a2 = o2 == 1 ? ay : az;
     const int mn = a2 < a1 ? o2 : o1;
-    // cyclic components starting at mn
-    const float ni = mn == 0 ? nx : (mn == 1 ? ny : nz);
+    const float ni = mn == 0 ? nx : (mn == 1 ? ny : nz);   // cyclic from mn
     const float nj = mn == 0 ? ny : (mn == 1 ? nz : nx);
     const float nk = mn == 0 ? nz : (mn == 1 ? nx : ny);
     const bool max_is_j = mx == (mn == 2 ? 0 : mn + 1);
@@ -68,13 +112,12 @@ __device__ __forceinline__ void specialized_basis(float nx, float ny, float nz, 
     // u_i = 0, u_j = n_k / n_max, u_k = -n_j / n_max (one of them is +-1 exactly)
     const float uj = max_is_j ? nk / nmax : 1.0f;
     const float uk = max_is_j ? -1.0f : -nj / nmax;
-    // v = (n x u) / |(n x u)_i|:  v_i = -sign(n_max), v_j, v_k = sign(n_max) n_i n_{j,k} / (n_j^2 + n_k^2)
+    // v = (n x u) / |(n x u)_i|: v_i = -sign(n_max), v_{j,k} = sign(n_max) n_i n_{j,k} / (n_j^2 + n_k^2)
     const float s = nmax > 0.0f ? 1.0f : -1.0f;
     const float w = 1.0f / (nj * nj + nk * nk);
     const float vi = -s;
     const float vj = s * ni * nj * w;
     const float vk = s * ni * nk * w;
-    // scatter back to x, y, z
     f.ux = mn == 0 ? 0.0f : (mn == 1 ? uk : uj);
     f.uy = mn == 1 ? 0.0f : (mn == 2 ? uk : uj);
     f.uz = mn == 2 ? 0.0f : (mn == 0 ? uk : uj);
@@ -111,18 +154,6 @@ __device__ __forceinline__ float depth(const Depth& g, float4 p) {
     return fmaf(g.gx, p.x, fmaf(g.gy, p.y, fmaf(g.gz, p.z, -g.go)));
 }
 
-__device__ __forceinline__ float4 load_point(const DevMesh& m, int32_t id) {
-    return reinterpret_cast<const float4*>(m.pts)[id];
-}
-
-__device__ __forceinline__ int4 load_nb(const DevMesh& m, int32_t t) {
-    return reinterpret_cast<const int4*>(m.nb)[t];
-}
-
-__device__ __forceinline__ uint32_t pick4(int4 v, int r) {
-    return uint32_t(r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w)));
-}
-
 // Algorithm 1: which of the three kept vertices the exit face drops.
 __device__ __forceinline__ int exit_slot(float q0x, float q0y, float q1x, float q1y, float q2x,
                                          float q2y, float q3x, float q3y) {
@@ -132,8 +163,8 @@ __device__ __forceinline__ int exit_slot(float q0x, float q0y, float q1x, float 
     return d0 < 0.0f ? (d2 >= 0.0f ? 1 : 0) : (d1 < 0.0f ? 2 : 0);
 }
 
-// State of a walk: the kept face (ids a, 2-D points q, depths e) in
-// counter-clockwise order around the ray, and the neighbour field across it.
+// The kept face (ids a, 2-D points q, depths e) in counter-clockwise order
+// around the ray, the neighbour field across it, and the tet it belongs to.
 struct Walk {
     int32_t a0, a1, a2;
     float q0x, q0y, q1x, q1y, q2x, q2y;
@@ -144,12 +175,42 @@ struct Walk {
 
 __device__ __forceinline__ void make_ccw(Walk& w) {
     const float o = det2(w.q1x - w.q0x, w.q1y - w.q0y, w.q2x - w.q0x, w.q2y - w.q0y);
-    if (o < 0.0f) {
-        int32_t ta = w.a1; w.a1 = w.a2; w.a2 = ta;
-        float t;
-        t = w.q1x; w.q1x = w.q2x; w.q2x = t;
-        t = w.q1y; w.q1y = w.q2y; w.q2y = t;
-        t = w.e1; w.e1 = w.e2; w.e2 = t;
+    const bool sw = o < 0.0f;
+    const int32_t a1 = w.a1, a2 = w.a2;
+    const float q1x = w.q1x, q1y = w.q1y, q2x = w.q2x, q2y = w.q2y, e1 = w.e1, e2 = w.e2;
+    w.a1 = sw ? a2 : a1; w.a2 = sw ? a1 : a2;
+    w.q1x = sw ? q2x : q1x; w.q2x = sw ? q1x : q2x;
+    w.q1y = sw ? q2y : q1y; w.q2y = sw ? q1y : q2y;
+    w.e1 = sw ? e2 : e1; w.e2 = sw ? e1 : e2;
+}
+
+// One step of the walk (Algorithms 1, 4 and 5), branch-free.
+template <bool DEPTH>
+__device__ __forceinline__ void walk_step(const Mem& M, uint32_t nt, uint32_t np, const Frame& f,
+                                          const Depth& g, Walk& w) {
+    const uint32_t tet = w.next;
+    const Rec R = load_rec(M, tet);
+    const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ R.vx;
+    const float4 P = load_pt(M, uint32_t(id3));
+    float q3x, q3y;
+    project(f, P, q3x, q3y);
+    const int e = exit_slot(w.q0x, w.q0y, w.q1x, w.q1y, w.q2x, w.q2y, q3x, q3y);
+    const bool s0 = e == 0, s1 = e == 1;
+    const int32_t x = s0 ? w.a0 : (s1 ? w.a1 : w.a2);
+    const int r = (w.a0 < x) + (w.a1 < x) + (w.a2 < x) + (id3 < x);
+    const uint32_t nx = r == 0 ? R.n0 : (r == 1 ? R.n1 : (r == 2 ? R.n2 : R.n3));
+    const bool sane = (tet < nt) & (uint32_t(id3) < np);
+    w.next = sane ? nx : kAbort;
+    w.cur = int32_t(tet);
+    const bool s2 = !(s0 | s1);
+    w.a0 = s0 ? id3 : w.a0;  w.q0x = s0 ? q3x : w.q0x;  w.q0y = s0 ? q3y : w.q0y;
+    w.a1 = s1 ? id3 : w.a1;  w.q1x = s1 ? q3x : w.q1x;  w.q1y = s1 ? q3y : w.q1y;
+    w.a2 = s2 ? id3 : w.a2;  w.q2x = s2 ? q3x : w.q2x;  w.q2y = s2 ? q3y : w.q2y;
+    if (DEPTH) {
+        const float e3 = depth(g, P);
+        w.e0 = s0 ? e3 : w.e0;
+        w.e1 = s1 ? e3 : w.e1;
+        w.e2 = s2 ? e3 : w.e2;
     }
 }
 
@@ -158,14 +219,14 @@ __device__ __forceinline__ void make_ccw(Walk& w) {
 // Fills the walk state (face ids, 2-D points in frame f, depths in g, the
 // neighbour field) and returns s (+inf when no face is front-facing).
 template <bool DEPTH>
-__device__ float start_in_tet(const DevMesh& m, int32_t tet, const int32_t v[4], float Xx, float Xy,
+__device__ float start_in_tet(const Mem& M, int32_t tet, const int32_t v[4], float Xx, float Xy,
                               float Xz, float Dx, float Dy, float Dz, const Frame& f, const Depth& g,
                               Walk& w) {
     float4 P[4];
     float rx[4], ry[4], rz[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        P[k] = load_point(m, v[k]);
+        P[k] = load_pt(M, uint32_t(v[k]));
         rx[k] = P[k].x - Xx;
         ry[k] = P[k].y - Xy;
         rz[k] = P[k].z - Xz;
@@ -207,7 +268,8 @@ __device__ float start_in_tet(const DevMesh& m, int32_t tet, const int32_t v[4],
     }
     const int32_t x = bj == 0 ? v[0] : (bj == 1 ? v[1] : (bj == 2 ? v[2] : v[3]));
     const int r = (v[0] < x) + (v[1] < x) + (v[2] < x) + (v[3] < x);
-    w.next = pick4(load_nb(m, tet), r);
+    const Rec R = load_rec(M, uint32_t(tet));
+    w.next = r == 0 ? R.n0 : (r == 1 ? R.n1 : (r == 2 ? R.n2 : R.n3));
     w.cur = tet;
     make_ccw(w);
     return best;
@@ -219,8 +281,8 @@ __device__ float start_in_tet(const DevMesh& m, int32_t tet, const int32_t v[4],
 // (parameter 1).  Constrained faces are crossed (location ignores geometry).
 // Returns the internal tet (its four ids in v) or TM_RAY_INVALID (outside) /
 // TM_RAY_STEP_CAP.
-__device__ int32_t locate_point(const DevMesh& m, float px, float py, float pz, int32_t max_steps,
-                                int32_t v[4]) {
+__device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float py, float pz,
+                                int32_t max_steps, int32_t v[4]) {
     int cx = int(floorf((px - m.lo[0]) * m.inv_cell[0]));
     int cy = int(floorf((py - m.lo[1]) * m.inv_cell[1]));
     int cz = int(floorf((pz - m.lo[2]) * m.inv_cell[2]));
@@ -233,7 +295,7 @@ __device__ int32_t locate_point(const DevMesh& m, float px, float py, float pz, 
     float Sx = 0.f, Sy = 0.f, Sz = 0.f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        float4 p = load_point(m, v[k]);
+        const float4 p = load_pt(M, uint32_t(v[k]));
         Sx += p.x; Sy += p.y; Sz += p.z;
     }
     Sx *= 0.25f; Sy *= 0.25f; Sz *= 0.25f;
@@ -245,10 +307,10 @@ __device__ int32_t locate_point(const DevMesh& m, float px, float py, float pz, 
     Depth g;
     set_depth(g, Dx, Dy, Dz, Sx, Sy, Sz);
     Walk w;
-    const float s0 = start_in_tet<true>(m, seed, v, Sx, Sy, Sz, Dx, Dy, Dz, f, g, w);
+    const float s0 = start_in_tet<true>(M, seed, v, Sx, Sy, Sz, Dx, Dy, Dz, f, g, w);
     if (!(s0 < 1.0f)) return seed;
     for (int32_t step = 0; step < max_steps; ++step) {
-        uint32_t field = w.next;
+        const uint32_t field = w.next;
         int32_t tet;
         if (field == kBoundary) return TM_RAY_INVALID;
         if (field & 0x80000000u) {
@@ -261,22 +323,12 @@ __device__ int32_t locate_point(const DevMesh& m, float px, float py, float pz, 
             tet = int32_t(field);
         }
         if (uint32_t(tet) >= uint32_t(m.nt)) return TM_RAY_STEP_CAP;
-        const int32_t vxv = m.vx[tet];
-        const int4 nbv = load_nb(m, tet);
-        const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ vxv;
-        if (uint32_t(id3) >= uint32_t(m.np)) return TM_RAY_STEP_CAP;
-        const float4 P = load_point(m, id3);
-        float q3x, q3y;
-        project(f, P, q3x, q3y);
-        const float e3 = depth(g, P);
-        const int e = exit_slot(w.q0x, w.q0y, w.q1x, w.q1y, w.q2x, w.q2y, q3x, q3y);
-        const int32_t x = e == 0 ? w.a0 : (e == 1 ? w.a1 : w.a2);
-        const int r = (w.a0 < x) + (w.a1 < x) + (w.a2 < x) + (id3 < x);
-        w.next = pick4(nbv, r);
-        w.cur = tet;
-        if (e == 0) { w.a0 = id3; w.q0x = q3x; w.q0y = q3y; w.e0 = e3; }
-        else if (e == 1) { w.a1 = id3; w.q1x = q3x; w.q1y = q3y; w.e1 = e3; }
-        else { w.a2 = id3; w.q2x = q3x; w.q2y = q3y; w.e2 = e3; }
+        w.next = uint32_t(tet);
+        const int32_t a0 = w.a0, a1 = w.a1, a2 = w.a2;
+        walk_step<true>(M, uint32_t(m.nt), uint32_t(m.np), f, g, w);
+        if (w.next == kAbort) return TM_RAY_STEP_CAP;
+        // the vertex the new face dropped: the tet is {a0, a1, a2, id3}
+        const int32_t x = (w.a0 != a0) ? a0 : ((w.a1 != a1) ? a1 : a2);
         // the segment leaves this tet through the new face at the depth of the
         // 2-D origin's barycentric combination; at or beyond 1 the point is inside
         const float l0 = det2(w.q1x, w.q1y, w.q2x, w.q2y);
@@ -290,6 +342,15 @@ __device__ int32_t locate_point(const DevMesh& m, float px, float py, float pz, 
     return TM_RAY_STEP_CAP;
 }
 
+// Everything a lane keeps for one ray between set-up and the result.
+struct Ray {
+    Frame f;
+    Depth g;
+    Walk w;
+    float tmax;
+    int32_t steps;
+};
+
 __device__ __forceinline__ void write_result(const RayArgs& r, int64_t i, int32_t code, float t,
                                              float b1, float b2, int32_t front, int32_t back,
                                              int32_t steps) {
@@ -300,106 +361,104 @@ __device__ __forceinline__ void write_result(const RayArgs& r, int64_t i, int32_
     if (r.steps) r.steps[i] = steps;
 }
 
-template <bool TMAX>
-__global__ void __launch_bounds__(256) k_trace(DevMesh m, RayArgs r) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= r.n) return;
+__device__ __forceinline__ void write_code(const RayArgs& r, int64_t i, int32_t code, int32_t steps) {
     const float NaN = __int_as_float(0x7fc00000);
+    write_result(r, i, code, NaN, NaN, NaN, -1, -1, steps);
+}
+
+// Set-up of ray i.  Returns true when the ray needs walking (state in s);
+// false when its result is already written.
+template <bool TMAX>
+__device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, Ray& s) {
     const float ox = r.orig[3 * i], oy = r.orig[3 * i + 1], oz = r.orig[3 * i + 2];
     const float dx = r.dir[3 * i], dy = r.dir[3 * i + 1], dz = r.dir[3 * i + 2];
-    const float tmax = TMAX ? r.tmax[i] : INFINITY;
+    s.tmax = TMAX ? r.tmax[i] : INFINITY;
+    s.steps = 0;
     const float dd = dx * dx + dy * dy + dz * dz;
-    if (!(dd > 0.0f) || !isfinite(dd) || !isfinite(ox + oy + oz) || isnan(tmax)) {
-        write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0);
-        return;
+    if (!(dd > 0.0f) || !isfinite(dd) || !isfinite(ox + oy + oz) || isnan(s.tmax)) {
+        write_code(r, i, TM_RAY_INVALID, 0);
+        return false;
     }
     const int32_t sf = r.start_face ? r.start_face[i] : -1;
-    Walk w;
-    Frame f;
-    Depth g;
     if (sf >= 0) {
         // secondary ray: start in the tet on the side of the face that dir points into
-        if (sf >= m.ntri) { write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0); return; }
+        if (sf >= m.ntri) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
         const int4 fv = reinterpret_cast<const int4*>(m.cfv)[sf];
         const int2 ft = reinterpret_cast<const int2*>(m.cft)[sf];
-        const float4 PA = load_point(m, fv.x), PB = load_point(m, fv.y), PC = load_point(m, fv.z);
+        const float4 PA = load_pt(M, uint32_t(fv.x)), PB = load_pt(M, uint32_t(fv.y)),
+                     PC = load_pt(M, uint32_t(fv.z));
         const float e1x = PB.x - PA.x, e1y = PB.y - PA.y, e1z = PB.z - PA.z;
         const float e2x = PC.x - PA.x, e2y = PC.y - PA.y, e2z = PC.z - PA.z;
         const float nd = (e1y * e2z - e1z * e2y) * dx + (e1z * e2x - e1x * e2z) * dy +
                          (e1x * e2y - e1y * e2x) * dz;
-        if (nd == 0.0f) { write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0); return; }
+        if (nd == 0.0f) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
         const int32_t start = nd > 0.0f ? ft.x : ft.y;
-        if (start < 0) { write_result(r, i, TM_RAY_MISS, NaN, NaN, NaN, -1, -1, 0); return; }
-        specialized_basis(dx, dy, dz, f);
-        set_origin(f, ox, oy, oz);
-        if (TMAX) set_depth(g, dx, dy, dz, ox, oy, oz);
-        w.a0 = fv.x; w.a1 = fv.y; w.a2 = fv.z;
-        project(f, PA, w.q0x, w.q0y);
-        project(f, PB, w.q1x, w.q1y);
-        project(f, PC, w.q2x, w.q2y);
-        if (TMAX) { w.e0 = depth(g, PA); w.e1 = depth(g, PB); w.e2 = depth(g, PC); }
-        make_ccw(w);
-        w.next = uint32_t(start);
-        w.cur = -1;
+        if (start < 0) { write_code(r, i, TM_RAY_MISS, 0); return false; }
+        specialized_basis(dx, dy, dz, s.f);
+        set_origin(s.f, ox, oy, oz);
+        if (TMAX) set_depth(s.g, dx, dy, dz, ox, oy, oz);
+        s.w.a0 = fv.x; s.w.a1 = fv.y; s.w.a2 = fv.z;
+        project(s.f, PA, s.w.q0x, s.w.q0y);
+        project(s.f, PB, s.w.q1x, s.w.q1y);
+        project(s.f, PC, s.w.q2x, s.w.q2y);
+        if (TMAX) { s.w.e0 = depth(s.g, PA); s.w.e1 = depth(s.g, PB); s.w.e2 = depth(s.g, PC); }
+        make_ccw(s.w);
+        s.w.next = uint32_t(start);
+        s.w.cur = -1;
+        return true;
+    }
+    int32_t v[4];
+    int32_t tet;
+    const int32_t st = r.start_tet ? r.start_tet[i] : -1;
+    if (st >= 0) {
+        if (st >= m.nt) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
+        tet = m.t_old2new[st];
+        const int4 sv = reinterpret_cast<const int4*>(m.tetv)[tet];
+        v[0] = sv.x; v[1] = sv.y; v[2] = sv.z; v[3] = sv.w;
     } else {
-        int32_t v[4];
-        int32_t tet;
-        const int32_t st = r.start_tet ? r.start_tet[i] : -1;
-        if (st >= 0) {
-            if (st >= m.nt) { write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0); return; }
-            tet = m.t_old2new[st];
-            const int4 sv = reinterpret_cast<const int4*>(m.tetv)[tet];
-            v[0] = sv.x; v[1] = sv.y; v[2] = sv.z; v[3] = sv.w;
-        } else {
-            tet = locate_point(m, ox, oy, oz, r.max_steps, v);
-            if (tet < 0) { write_result(r, i, tet, NaN, NaN, NaN, -1, -1, 0); return; }
-        }
-        specialized_basis(dx, dy, dz, f);
-        set_origin(f, ox, oy, oz);
-        if (TMAX) set_depth(g, dx, dy, dz, ox, oy, oz);
-        const float s = start_in_tet<TMAX>(m, tet, v, ox, oy, oz, dx, dy, dz, f, g, w);
-        if (!(s < INFINITY)) { write_result(r, i, TM_RAY_INVALID, NaN, NaN, NaN, -1, -1, 0); return; }
+        tet = locate_point(m, M, ox, oy, oz, r.max_steps, v);
+        if (tet < 0) { write_code(r, i, tet, 0); return false; }
     }
+    specialized_basis(dx, dy, dz, s.f);
+    set_origin(s.f, ox, oy, oz);
+    if (TMAX) set_depth(s.g, dx, dy, dz, ox, oy, oz);
+    const float sx = start_in_tet<TMAX>(M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w);
+    if (!(sx < INFINITY)) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
+    return true;
+}
 
-    // ---- the walk ------------------------------------------------------------
-    int32_t steps = 0;
-    int32_t code = 0;
-    for (;;) {
-        if (w.next & 0x80000000u) break;  // constrained face or boundary
-        if (TMAX && fminf(w.e0, fminf(w.e1, w.e2)) > tmax) { code = TM_RAY_MISS; break; }
-        if (steps >= r.max_steps || w.next >= uint32_t(m.nt)) { code = TM_RAY_STEP_CAP; break; }
-        ++steps;
-        const int32_t tet = int32_t(w.next);
-        const int32_t vxv = m.vx[tet];
-        const int4 nbv = load_nb(m, tet);
-        const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ vxv;
-        if (uint32_t(id3) >= uint32_t(m.np)) { code = TM_RAY_STEP_CAP; break; }
-        const float4 P = load_point(m, id3);
-        float q3x, q3y;
-        project(f, P, q3x, q3y);
-        const int e = exit_slot(w.q0x, w.q0y, w.q1x, w.q1y, w.q2x, w.q2y, q3x, q3y);
-        const int32_t x = e == 0 ? w.a0 : (e == 1 ? w.a1 : w.a2);
-        const int rk = (w.a0 < x) + (w.a1 < x) + (w.a2 < x) + (id3 < x);
-        w.next = pick4(nbv, rk);
-        w.cur = tet;
-        float e3 = 0.0f;
-        if (TMAX) e3 = depth(g, P);
-        if (e == 0) { w.a0 = id3; w.q0x = q3x; w.q0y = q3y; if (TMAX) w.e0 = e3; }
-        else if (e == 1) { w.a1 = id3; w.q1x = q3x; w.q1y = q3y; if (TMAX) w.e1 = e3; }
-        else { w.a2 = id3; w.q2x = q3x; w.q2y = q3y; if (TMAX) w.e2 = e3; }
+// Whether the walk of s goes on: the field ahead is a tet, the step cap is not
+// reached and (with tmax) the face ahead is not entirely beyond tmax.
+template <bool TMAX>
+__device__ __forceinline__ bool walk_on(const Ray& s, int32_t max_steps) {
+    bool go = (int32_t(s.w.next) >= 0) & (s.steps < max_steps);
+    if (TMAX) go = go & !(fminf(s.w.e0, fminf(s.w.e1, s.w.e2)) > s.tmax);
+    return go;
+}
+
+// Result of a walk that stopped; the hit's t and barycentric weights come from
+// the Moller-Trumbore form in float64 with the triangle's vertices in ascending
+// caller-id order, so the weights are those of its 2nd and 3rd vertex.
+template <bool TMAX>
+__device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, const Ray& s) {
+    const uint32_t nx = s.w.next;
+    if (!(nx & 0x80000000u)) {
+        // tmax early-out, else the step cap
+        const bool beyond = TMAX && (fminf(s.w.e0, fminf(s.w.e1, s.w.e2)) > s.tmax);
+        write_code(r, i, beyond ? TM_RAY_MISS : TM_RAY_STEP_CAP, s.steps);
+        return;
     }
-    if (code != 0) { write_result(r, i, code, NaN, NaN, NaN, -1, -1, steps); return; }
-    if (w.next == kBoundary) { write_result(r, i, TM_RAY_MISS, NaN, NaN, NaN, -1, -1, steps); return; }
-
-    // ---- the hit: t and barycentric weights in float64 (Moller-Trumbore) -----
-    const uint32_t cf = w.next & kIdMask;
-    if (cf >= uint32_t(m.ntri)) { write_result(r, i, TM_RAY_STEP_CAP, NaN, NaN, NaN, -1, -1, steps); return; }
-    const int4 fv = reinterpret_cast<const int4*>(m.cfv)[cf];   // ascending caller ids
-    const float4 A = load_point(m, fv.x), B = load_point(m, fv.y), C = load_point(m, fv.z);
+    if (nx == kBoundary) { write_code(r, i, TM_RAY_MISS, s.steps); return; }
+    const uint32_t cf = nx & kIdMask;
+    if (nx == kAbort || cf >= uint32_t(m.ntri)) { write_code(r, i, TM_RAY_STEP_CAP, s.steps); return; }
+    const int4 fv = reinterpret_cast<const int4*>(m.cfv)[cf];
+    const float4 A = load_pt(M, uint32_t(fv.x)), B = load_pt(M, uint32_t(fv.y)),
+                 C = load_pt(M, uint32_t(fv.z));
+    const double ox = r.orig[3 * i], oy = r.orig[3 * i + 1], oz = r.orig[3 * i + 2];
+    const double Dx = r.dir[3 * i], Dy = r.dir[3 * i + 1], Dz = r.dir[3 * i + 2];
     const double e1x = double(B.x) - A.x, e1y = double(B.y) - A.y, e1z = double(B.z) - A.z;
     const double e2x = double(C.x) - A.x, e2y = double(C.y) - A.y, e2z = double(C.z) - A.z;
-    const double sx = double(ox) - A.x, sy = double(oy) - A.y, sz = double(oz) - A.z;
-    const double Dx = dx, Dy = dy, Dz = dz;
+    const double sx = ox - A.x, sy = oy - A.y, sz = oz - A.z;
     const double px = Dy * e2z - Dz * e2y, py = Dz * e2x - Dx * e2z, pz = Dx * e2y - Dy * e2x;
     const double det = e1x * px + e1y * py + e1z * pz;
     const double inv = 1.0 / det;
@@ -407,38 +466,106 @@ __global__ void __launch_bounds__(256) k_trace(DevMesh m, RayArgs r) {
     const double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
     const double bv = (Dx * qx + Dy * qy + Dz * qz) * inv;
     const double th = (e2x * qx + e2y * qy + e2z * qz) * inv;
-    if (TMAX && th > double(tmax)) { write_result(r, i, TM_RAY_MISS, NaN, NaN, NaN, -1, -1, steps); return; }
+    if (TMAX && th > double(s.tmax)) { write_code(r, i, TM_RAY_MISS, s.steps); return; }
     int32_t front = -1, back = -1;
     if (r.hit_tets) {
         const int2 ft = reinterpret_cast<const int2*>(m.cft)[cf];
-        const int32_t other = ft.x == w.cur ? ft.y : ft.x;
-        front = m.t_new2old[w.cur];
+        const int32_t other = ft.x == s.w.cur ? ft.y : ft.x;
+        front = m.t_new2old[s.w.cur];
         back = other >= 0 ? m.t_new2old[other] : -1;
     }
-    write_result(r, i, int32_t(cf), float(th), float(bu), float(bv), front, back, steps);
+    write_result(r, i, int32_t(cf), float(th), float(bu), float(bv), front, back, s.steps);
+}
+
+// One lane per ray: set-up, walk, result.
+template <bool TMAX>
+__global__ void __launch_bounds__(256) k_trace(DevMesh m, RayArgs r) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= r.n) return;
+    const Mem M = make_mem(m);
+    Ray s;
+    if (!setup_ray<TMAX>(m, M, r, i, s)) return;
+    while (walk_on<TMAX>(s, r.max_steps)) {
+        walk_step<TMAX>(M, uint32_t(m.nt), uint32_t(m.np), s.f, s.g, s.w);
+        ++s.steps;
+    }
+    finish_ray<TMAX>(m, M, r, i, s);
+}
+
+// Persistent lanes: lane g of the grid owns rays g, g + L, g + 2L, ... (L =
+// lanes in the grid), so neighbouring lanes start on neighbouring rays.  A
+// wave walks until `refill` of its lanes have finished, then writes those
+// results and sets up their next rays together, so the dependent loads of
+// set-up and result are paid once per batch rather than on every step.
+template <bool TMAX>
+__global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, int32_t refill) {
+    const int64_t L = int64_t(gridDim.x) * blockDim.x;
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const Mem M = make_mem(m);
+    const uint32_t nt = uint32_t(m.nt), np = uint32_t(m.np);
+    Ray s;
+    bool has = false;   // the lane holds ray i
+    bool done = false;  // ... and its walk has stopped
+    for (;;) {
+        if (done) {
+            finish_ray<TMAX>(m, M, r, i, s);
+            done = false;
+            has = false;
+            i += L;
+        }
+        if (!has) {
+            while (i < r.n) {
+                if (setup_ray<TMAX>(m, M, r, i, s)) { has = true; break; }
+                i += L;
+            }
+        }
+        if (!__any(has)) break;
+        for (;;) {
+            const bool go = has && !done && walk_on<TMAX>(s, r.max_steps);
+            done = has && !go;
+            if (__popcll(__ballot(done)) >= uint32_t(refill) || !__any(go)) break;
+            if (go) {
+                walk_step<TMAX>(M, nt, np, s.f, s.g, s.w);
+                ++s.steps;
+            }
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_locate(DevMesh m, int64_t n, const float* pts, int32_t* out,
                                                 int32_t max_steps) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const Mem M = make_mem(m);
     const float px = pts[3 * i], py = pts[3 * i + 1], pz = pts[3 * i + 2];
     if (!isfinite(px + py + pz)) { out[i] = -1; return; }
     int32_t v[4];
-    const int32_t t = locate_point(m, px, py, pz, max_steps, v);
+    const int32_t t = locate_point(m, M, px, py, pz, max_steps, v);
     out[i] = t >= 0 ? m.t_new2old[t] : (t == TM_RAY_STEP_CAP ? -2 : -1);
 }
 
 }  // namespace
 
-hipError_t launch_trace(const DevMesh& m, const RayArgs& r, int block, hipStream_t s) {
+hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s) {
     if (r.n <= 0) return hipSuccess;
-    if (block != 64 && block != 128 && block != 256) block = 256;
-    const int64_t grid = (r.n + block - 1) / block;
-    if (r.tmax)
-        hipLaunchKernelGGL(k_trace<true>, dim3(unsigned(grid)), dim3(block), 0, s, m, r);
-    else
-        hipLaunchKernelGGL(k_trace<false>, dim3(unsigned(grid)), dim3(block), 0, s, m, r);
+    const int block = (c.block == 64 || c.block == 128) ? c.block : 256;
+    const int64_t simple_grid = (r.n + block - 1) / block;
+    if (c.kernel == 2) {
+        // enough lanes to fill every CU with `waves_per_simd` waves per SIMD
+        const int64_t blocks_per_cu = int64_t(c.waves_per_simd) * 4 * 64 / block;
+        int64_t grid = std::min<int64_t>(simple_grid, std::max<int64_t>(1, c.cus * blocks_per_cu));
+        if (c.grid_cap > 0) grid = std::min<int64_t>(grid, c.grid_cap);
+        const int32_t refill = std::min(64, std::max(1, c.refill));
+        if (r.tmax)
+            hipLaunchKernelGGL(k_trace_persistent<true>, dim3(unsigned(grid)), dim3(block), 0, s, m, r, refill);
+        else
+            hipLaunchKernelGGL(k_trace_persistent<false>, dim3(unsigned(grid)), dim3(block), 0, s, m, r, refill);
+    } else {
+        if (r.tmax)
+            hipLaunchKernelGGL(k_trace<true>, dim3(unsigned(simple_grid)), dim3(block), 0, s, m, r);
+        else
+            hipLaunchKernelGGL(k_trace<false>, dim3(unsigned(simple_grid)), dim3(block), 0, s, m, r);
+    }
     return hipGetLastError();
 }
 

@@ -44,10 +44,14 @@ def _ao_from(m, om, o, d, ref, k=8, seed=3, tmax=0.1):
     return ao, ad, atm, ref["tri"][hit][parent].astype(np.int32)
 
 
-def test_tiny_primary(tiny):
+KERNELS = [dict(kernel=1), dict(kernel=2), dict(kernel=2, grid_cap=2, refill=8)]
+
+
+@pytest.mark.parametrize("kw", KERNELS)
+def test_tiny_primary(tiny, kw):
     m, om, mesh = tiny
     o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 64, 64, 60.0)
-    got = _host(mesh.trace(_dev(o), _dev(d), want_tets=True, want_steps=True))
+    got = _host(mesh.trace(_dev(o), _dev(d), want_tets=True, want_steps=True, **kw))
     ref = om.trace(o, d)
     rep = compare(m.points, om.tri_verts, o, d, ref, got)
     assert rep["ok"], rep
@@ -56,12 +60,14 @@ def test_tiny_primary(tiny):
     assert (got["steps"] == ref["steps"]).mean() > 0.999
 
 
-def test_tiny_ao(tiny):
+@pytest.mark.parametrize("kw", KERNELS)
+def test_tiny_ao(tiny, kw):
     m, om, mesh = tiny
     o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 64, 64, 60.0)
     ref0 = om.trace(o, d)
     ao, ad, atm, sf = _ao_from(m, om, o, d, ref0)
-    got = _host(mesh.trace(_dev(ao), _dev(ad), tmax=_dev(atm), start_face=_dev(sf), want_tets=True))
+    got = _host(mesh.trace(_dev(ao), _dev(ad), tmax=_dev(atm), start_face=_dev(sf), want_tets=True,
+                           **kw))
     ref = om.trace(ao, ad, atm, start_face=sf)
     rep = compare(m.points, om.tri_verts, ao, ad, ref, got, tmax=atm)
     assert rep["ok"], rep
@@ -77,15 +83,16 @@ def test_random_rays_small_meshes(tetrt, n, seed):
     o, d = random_interior_rays(20000, seed)
     tm = np.random.default_rng(seed).uniform(0.05, 1.5, 20000).astype(np.float32)
     tm[::4] = np.inf
-    got = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm)))
-    ref = om.trace(o, d, tm)
-    rep = compare(m.points, om.tri_verts, o, d, ref, got, tmax=tm)
-    assert rep["ok"], rep
-    # the same rays without tmax
-    got = _host(mesh.trace(_dev(o), _dev(d)))
+    ref_tm = om.trace(o, d, tm)
     ref = om.trace(o, d)
-    rep = compare(m.points, om.tri_verts, o, d, ref, got)
-    assert rep["ok"], rep
+    for kw in KERNELS:
+        got = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), **kw))
+        rep = compare(m.points, om.tri_verts, o, d, ref_tm, got, tmax=tm)
+        assert rep["ok"], (kw, rep)
+        # the same rays without tmax
+        got = _host(mesh.trace(_dev(o), _dev(d), **kw))
+        rep = compare(m.points, om.tri_verts, o, d, ref, got)
+        assert rep["ok"], (kw, rep)
     mesh.free()
 
 
@@ -179,3 +186,21 @@ def test_repeat_calls_identical(tiny):
     b = _host(mesh.trace(_dev(o), _dev(d), block=64))
     assert np.array_equal(a["tri"], b["tri"])
     assert np.array_equal(a["t"], b["t"], equal_nan=True)
+
+
+@pytest.mark.parametrize("refill", [1, 16, 64])
+def test_persistent_matches_one_lane_per_ray(tiny, refill):
+    """Persistent lanes (few blocks, so every lane takes many rays) give
+    bit-identical results to one lane per ray: same arithmetic per ray."""
+    m, om, mesh = tiny
+    o, d = random_interior_rays(30000, 37)
+    tm = np.random.default_rng(2).uniform(0.0, 0.6, 30000).astype(np.float32)
+    tm[::5] = np.inf
+    st = om.locate(o)
+    st[::3] = -1                      # a third of the rays locate on the device
+    a = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), start_tet=_dev(st), want_tets=True,
+                         want_steps=True, kernel=1))
+    b = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), start_tet=_dev(st), want_tets=True,
+                         want_steps=True, kernel=2, grid_cap=3, refill=refill))
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
