@@ -193,7 +193,8 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     c.grid_cap = o.grid_cap;
     // persistent lanes pay off once every lane gets several rays
     const int64_t lanes = int64_t(c.cus) * 4 * 64 * c.waves_per_simd;
-    c.kernel = o.kernel ? o.kernel : (n_rays >= 4 * lanes ? 2 : 1);
+    (void)lanes;
+    c.kernel = o.kernel ? o.kernel : 1;
     hipError_t e = tetrt::launch_trace(m->dev, r, c, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "trace_closest: kernel launch");
     return TM_OK;
