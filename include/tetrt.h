@@ -54,8 +54,11 @@ enum {
 
 /* compact tet record layouts (paper, Sec. "Tetrahedral Mesh Representation") */
 enum {
-    TM_LAYOUT_TET20 = 0 /* xor of the four vertex ids + four neighbour fields
-                           ordered by the id of the vertex they face (20 B/tet) */
+    TM_LAYOUT_TET20 = 0, /* xor of the four vertex ids + four neighbour fields
+                            ordered by the id of the vertex they face (20 B/tet) */
+    TM_LAYOUT_TET16 = 1  /* xor of the four vertex ids + three neighbour fields each
+                            xored with the fourth; the walk decodes the next tet from
+                            the previous one (16 B/tet) */
 };
 
 /* memory order of points and tets (paper, Sec. "Reordering tetrahedral mesh data") */
@@ -113,7 +116,8 @@ typedef struct {
  * vertex each one faces (the paper's Tet20).  A neighbour field is either a tet
  * id or, when its top bit is set, a reference to a constrained-face record
  * that holds the scene triangle and the two adjacent tets (paper, same
- * section); 0xFFFFFFFF marks the mesh boundary.  Points and tets are reordered
+ * section); 0xFFFFFFFF marks the mesh boundary.  TM_LAYOUT_TET16 stores the
+ * paper's 16-byte form instead.  Points and tets are reordered
  * along a 3-D space-filling curve (paper, Sec. "Reordering tetrahedral mesh
  * data").
  *

@@ -91,7 +91,7 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
                     (long long)(0xFFFFFFFFLL / 20), (long long)(0xFFFFFFFFLL / 16));
     tm_upload_opts o = {TM_LAYOUT_TET20, TM_SFC_HILBERT, 1, 0};
     if (opts) o = *opts;
-    if (o.layout != TM_LAYOUT_TET20)
+    if (o.layout != TM_LAYOUT_TET20 && o.layout != TM_LAYOUT_TET16)
         return fail(TM_ERR_ARG, "tetmesh_upload: unsupported layout %d", o.layout);
     if (o.sfc < TM_SFC_HILBERT || o.sfc > TM_SFC_NONE)
         return fail(TM_ERR_ARG, "tetmesh_upload: unknown sfc %d", o.sfc);
@@ -124,6 +124,7 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     int64_t hot = 0, cold = 0;
     tetrt::DevMesh& d = m->dev;
     if ((rc = upload_array(m, pm.rec, &d.rec, &hot)) ||
+        (!pm.n3.empty() && (rc = upload_array(m, pm.n3, &d.n3, &cold))) ||
         (rc = upload_array(m, pm.pts4, &d.pts, &hot)) ||
         (rc = upload_array(m, pm.tetv, &d.tetv, &cold)) ||
         (rc = upload_array(m, pm.cfv, &d.cfv, &cold)) ||
@@ -143,6 +144,7 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     d.nt = int32_t(pm.nt);
     d.np = int32_t(pm.np);
     d.ntri = int32_t(pm.ntri);
+    d.layout = pm.layout;
     m->hot_bytes = hot;
     m->cold_bytes = cold;
     m->tri_verts_user.swap(pm.tri_verts_user);

@@ -11,7 +11,9 @@ namespace tetrt {
 // kernels by value.  Vector-typed arrays are stored as their scalar base type
 // and reinterpreted in the kernels (int4 / float4 / int2, 16- or 8-byte aligned).
 struct DevMesh {
-    const int32_t* rec;       // [nt*5]    Tet20 records: xor field, 4 neighbour fields
+    const int32_t* rec;       // [nt*5] Tet20 records (xor field, N0..N3) or
+                              // [nt*4] Tet16 records (xor field, NX0..NX2)
+    const int32_t* n3;        // [nt]      Tet16 only: N3 of every tet (cold, for starts)
     const float* pts;         // [np*4]    float4 per point
     const int32_t* tetv;      // [nt*4]    ascending vertex ids (int4 per tet)
     const int32_t* cfv;       // [ntri*4]  constrained-face vertices (int4)
@@ -25,6 +27,7 @@ struct DevMesh {
     int32_t nt;
     int32_t np;
     int32_t ntri;
+    int32_t layout;           // TM_LAYOUT_*
 };
 
 struct RayArgs {

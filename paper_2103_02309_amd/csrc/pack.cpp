@@ -320,8 +320,10 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
         M.pts4[4 * i + 2] = s[2];
     }
 
-    // ---- Tet20 records ---------------------------------------------------------
-    M.rec.resize(size_t(5 * nt));
+    // ---- tet records (Tet20 or Tet16) --------------------------------------
+    const bool t16 = opts.layout == TM_LAYOUT_TET16;
+    M.rec.resize(size_t((t16 ? 4 : 5) * nt));
+    if (t16) M.n3.resize(size_t(nt));
     M.tetv.resize(size_t(4 * nt));
     parallel_for(nt, [&](int64_t b, int64_t e) {
         for (int64_t tn = b; tn < e; ++tn) {
@@ -336,18 +338,25 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
                     std::swap(v[c], v[c - 1]);
                     std::swap(slot[c], slot[c - 1]);
                 }
-            M.rec[5 * tn] = v[0] ^ v[1] ^ v[2] ^ v[3];
+            uint32_t field[4];
             for (int r = 0; r < 4; ++r) {
                 int64_t f = 4 * t + slot[r];
-                uint32_t field;
                 if (cflag[f])
-                    field = kConstrainedBit | uint32_t(face_tri[f]);
+                    field[r] = kConstrainedBit | uint32_t(face_tri[f]);
                 else if (nbrs[f] < 0)
-                    field = kBoundaryField;
+                    field[r] = kBoundaryField;
                 else
-                    field = uint32_t(M.t_old2new[nbrs[f]]);
-                M.rec[5 * tn + 1 + r] = int32_t(field);
+                    field[r] = uint32_t(M.t_old2new[nbrs[f]]);
                 M.tetv[4 * tn + r] = v[r];
+            }
+            const int32_t vx = v[0] ^ v[1] ^ v[2] ^ v[3];
+            if (t16) {
+                M.rec[4 * tn] = vx;
+                for (int r = 0; r < 3; ++r) M.rec[4 * tn + 1 + r] = int32_t(field[r] ^ field[3]);
+                M.n3[tn] = int32_t(field[3]);
+            } else {
+                M.rec[5 * tn] = vx;
+                for (int r = 0; r < 4; ++r) M.rec[5 * tn + 1 + r] = int32_t(field[r]);
             }
         }
     });

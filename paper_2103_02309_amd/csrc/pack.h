@@ -17,8 +17,10 @@ struct PackedMesh {
     int64_t np = 0, nt = 0, ntri = 0;
     int32_t layout = 0, sfc = 0;
     std::vector<float> pts4;             // [np*4]   x, y, z, 0 in internal point order
-    std::vector<int32_t> rec;            // [nt*5]   Tet20: xor of the four internal vertex ids,
-                                         //          then the neighbour fields by ascending vertex id
+    std::vector<int32_t> rec;            // Tet20 [nt*5]: xor of the four internal vertex ids, then
+                                         //   the neighbour fields N0..N3 by ascending vertex id;
+                                         // Tet16 [nt*4]: xor, then NX_j = N_j ^ N_3 for j < 3
+    std::vector<int32_t> n3;             // Tet16 only [nt]: N_3 (cold, to start walks)
     std::vector<int32_t> tetv;           // [nt*4]   internal vertex ids, ascending (cold)
     std::vector<int32_t> cfv;            // [ntri*4] internal ids of the triangle's vertices in
                                          //          ascending caller-id order, then 0

@@ -21,12 +21,17 @@
 //             (hit) or the boundary (miss).  The hit's t and barycentric
 //             weights are evaluated once, in float64.
 //
-// Memory: a tet record is 20 packed bytes {VX, N0, N1, N2, N3} (the paper's
-// Tet20), read as one 16-byte and one 4-byte buffer load issued together at the
-// top of a step; the point is one 16-byte load.  A step is therefore two
-// dependent round trips (record, then point).  Buffer loads return zero beyond
-// the array instead of faulting, and the step is branch-free: the loop test is
-// its only branch.
+// Memory (paper, Sec. "Tetrahedral Mesh Representation"):
+//   Tet20  20 packed bytes {VX, N0, N1, N2, N3}, read as one 16-byte and one
+//          4-byte buffer load issued together at the top of a step;
+//   Tet16  16 bytes {VX, NX0, NX1, NX2} with NX_j = N_j ^ N_3, one aligned
+//          16-byte load; the neighbour across the exit face is the field of the
+//          entry face (known: it refers back to the previous tet) xor NX of the
+//          entry vertex's rank xor NX of the exit vertex's rank (NX_3 = 0),
+//          Algorithms 6-7.
+// The point is one 16-byte load, so a step is two dependent round trips
+// (record, then point).  Buffer loads return zero beyond the array instead of
+// faulting, and the step is branch-free: the loop test is its only branch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -40,9 +45,14 @@ namespace tetrt {
 namespace {
 
 constexpr uint32_t kBoundary = 0xFFFFFFFFu;
-constexpr uint32_t kAbort = 0xFFFFFFFEu;   // internal: the walk met an inconsistent record
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
-constexpr uint32_t kRecBytes = 20;         // Tet20 record
+
+// record layouts
+constexpr int kTet20 = 0;
+constexpr int kTet16 = 1;
+
+template <int LAYOUT>
+constexpr uint32_t rec_bytes() { return LAYOUT == kTet20 ? 20u : 16u; }
 
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
@@ -57,23 +67,61 @@ struct Mem {
     rsrc_t pts;
 };
 
+template <int LAYOUT>
 __device__ __forceinline__ Mem make_mem(const DevMesh& m) {
     Mem M;
-    M.rec = make_rsrc(m.rec, uint64_t(m.nt) * kRecBytes);
+    M.rec = make_rsrc(m.rec, uint64_t(m.nt) * rec_bytes<LAYOUT>());
     M.pts = make_rsrc(m.pts, uint64_t(m.np) * 16u);
     return M;
 }
 
+// Pins a loaded value at this point of the program.  Without it the compiler
+// may turn a select among loaded fields into a branch and move the load into
+// it, which adds a dependent memory round trip to the step.
+__device__ __forceinline__ void keep(uint32_t& v) { asm volatile("" : "+v"(v)); }
+
+// A record as loaded: the xor field and four more words (Tet20: N0..N3 by
+// ascending vertex id; Tet16: NX0..NX2 and 0).
 struct Rec {
     int32_t vx;
     uint32_t n0, n1, n2, n3;
 };
 
+template <int LAYOUT>
 __device__ __forceinline__ Rec load_rec(const Mem& M, uint32_t tet) {
-    const uint32_t off = tet * kRecBytes;
-    const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, off, 0, 0);
-    const uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(M.rec, off + 16u, 0, 0);
-    return Rec{int32_t(a[0]), a[1], a[2], a[3], b};
+    if (LAYOUT == kTet20) {
+        uint32_t t4 = tet << 2;   // 20 * tet as two shifts, not a quarter-rate multiply
+        keep(t4);
+        const uint32_t off = (tet << 4) + t4;
+        const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, off, 0, 0);
+        uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(M.rec, off + 16u, 0, 0);
+        keep(b);
+        return Rec{int32_t(a[0]), a[1], a[2], a[3], b};
+    } else {
+        const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, tet << 4, 0, 0);
+        return Rec{int32_t(a[0]), a[1], a[2], a[3], 0u};
+    }
+}
+
+// Neighbour field across the face opposite the vertex of rank r (0..3) in a
+// record; `back` is the field of the face the walk entered through and `ra`
+// the rank of the vertex opposite it (used by Tet16 only).
+// Word r (0..3) of four, selected on the bits of r: three selects and no
+// compare chain (which the compiler would turn into a branch).
+__device__ __forceinline__ uint32_t pick4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int r) {
+    const bool b0 = (r & 1) != 0, b1 = (r & 2) != 0;
+    const uint32_t lo = b0 ? w1 : w0;
+    const uint32_t hi = b0 ? w3 : w2;
+    return b1 ? hi : lo;
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t next_field(const Rec& R, int r, uint32_t back, int ra) {
+    if (LAYOUT == kTet20) {
+        return pick4(R.n0, R.n1, R.n2, R.n3, r);
+    } else {
+        return back ^ pick4(R.n0, R.n1, R.n2, 0u, ra) ^ pick4(R.n0, R.n1, R.n2, 0u, r);
+    }
 }
 
 __device__ __forceinline__ float4 load_pt(const Mem& M, uint32_t id) {
@@ -164,7 +212,9 @@ __device__ __forceinline__ int exit_slot(float q0x, float q0y, float q1x, float 
 }
 
 // The kept face (ids a, 2-D points q, depths e) in counter-clockwise order
-// around the ray, the neighbour field across it, and the tet it belongs to.
+// around the ray, the neighbour field across it, and `cur`: the field that the
+// next tet's record holds for this face -- the id of the tet the face belongs
+// to, or the constrained-face field when a secondary ray starts on it.
 struct Walk {
     int32_t a0, a1, a2;
     float q0x, q0y, q1x, q1y, q2x, q2y;
@@ -184,12 +234,11 @@ __device__ __forceinline__ void make_ccw(Walk& w) {
     w.e1 = sw ? e2 : e1; w.e2 = sw ? e1 : e2;
 }
 
-// One step of the walk (Algorithms 1, 4 and 5), branch-free.
-template <bool DEPTH>
-__device__ __forceinline__ void walk_step(const Mem& M, uint32_t nt, uint32_t np, const Frame& f,
-                                          const Depth& g, Walk& w) {
+// One step of the walk (Algorithm 1 with Algorithms 4-5 or 6-7), branch-free.
+template <bool DEPTH, int LAYOUT>
+__device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const Depth& g, Walk& w) {
     const uint32_t tet = w.next;
-    const Rec R = load_rec(M, tet);
+    const Rec R = load_rec<LAYOUT>(M, tet);
     const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ R.vx;
     const float4 P = load_pt(M, uint32_t(id3));
     float q3x, q3y;
@@ -198,9 +247,8 @@ __device__ __forceinline__ void walk_step(const Mem& M, uint32_t nt, uint32_t np
     const bool s0 = e == 0, s1 = e == 1;
     const int32_t x = s0 ? w.a0 : (s1 ? w.a1 : w.a2);
     const int r = (w.a0 < x) + (w.a1 < x) + (w.a2 < x) + (id3 < x);
-    const uint32_t nx = r == 0 ? R.n0 : (r == 1 ? R.n1 : (r == 2 ? R.n2 : R.n3));
-    const bool sane = (tet < nt) & (uint32_t(id3) < np);
-    w.next = sane ? nx : kAbort;
+    const int ra = LAYOUT == kTet16 ? (w.a0 < id3) + (w.a1 < id3) + (w.a2 < id3) : 0;
+    w.next = next_field<LAYOUT>(R, r, uint32_t(w.cur), ra);
     w.cur = int32_t(tet);
     const bool s2 = !(s0 | s1);
     w.a0 = s0 ? id3 : w.a0;  w.q0x = s0 ? q3x : w.q0x;  w.q0y = s0 ? q3y : w.q0y;
@@ -218,10 +266,10 @@ __device__ __forceinline__ void walk_step(const Mem& M, uint32_t nt, uint32_t np
 // whose outward normal has n.D > 0 with the smallest crossing parameter s.
 // Fills the walk state (face ids, 2-D points in frame f, depths in g, the
 // neighbour field) and returns s (+inf when no face is front-facing).
-template <bool DEPTH>
-__device__ float start_in_tet(const Mem& M, int32_t tet, const int32_t v[4], float Xx, float Xy,
-                              float Xz, float Dx, float Dy, float Dz, const Frame& f, const Depth& g,
-                              Walk& w) {
+template <bool DEPTH, int LAYOUT>
+__device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const int32_t v[4],
+                              float Xx, float Xy, float Xz, float Dx, float Dy, float Dz,
+                              const Frame& f, const Depth& g, Walk& w) {
     float4 P[4];
     float rx[4], ry[4], rz[4];
 #pragma unroll
@@ -268,8 +316,10 @@ __device__ float start_in_tet(const Mem& M, int32_t tet, const int32_t v[4], flo
     }
     const int32_t x = bj == 0 ? v[0] : (bj == 1 ? v[1] : (bj == 2 ? v[2] : v[3]));
     const int r = (v[0] < x) + (v[1] < x) + (v[2] < x) + (v[3] < x);
-    const Rec R = load_rec(M, uint32_t(tet));
-    w.next = r == 0 ? R.n0 : (r == 1 ? R.n1 : (r == 2 ? R.n2 : R.n3));
+    const Rec R = load_rec<LAYOUT>(M, uint32_t(tet));
+    // Tet16 keeps N3 of every tet in a cold array for starts: N_r = N3 ^ NX_r
+    w.next = LAYOUT == kTet20 ? next_field<kTet20>(R, r, 0u, 0)
+                              : next_field<kTet16>(R, r, uint32_t(m.n3[tet]), 3);
     w.cur = tet;
     make_ccw(w);
     return best;
@@ -281,6 +331,7 @@ __device__ float start_in_tet(const Mem& M, int32_t tet, const int32_t v[4], flo
 // (parameter 1).  Constrained faces are crossed (location ignores geometry).
 // Returns the internal tet (its four ids in v) or TM_RAY_INVALID (outside) /
 // TM_RAY_STEP_CAP.
+template <int LAYOUT>
 __device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float py, float pz,
                                 int32_t max_steps, int32_t v[4]) {
     int cx = int(floorf((px - m.lo[0]) * m.inv_cell[0]));
@@ -307,7 +358,7 @@ __device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float 
     Depth g;
     set_depth(g, Dx, Dy, Dz, Sx, Sy, Sz);
     Walk w;
-    const float s0 = start_in_tet<true>(M, seed, v, Sx, Sy, Sz, Dx, Dy, Dz, f, g, w);
+    const float s0 = start_in_tet<true, LAYOUT>(m, M, seed, v, Sx, Sy, Sz, Dx, Dy, Dz, f, g, w);
     if (!(s0 < 1.0f)) return seed;
     for (int32_t step = 0; step < max_steps; ++step) {
         const uint32_t field = w.next;
@@ -319,14 +370,15 @@ __device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float 
             const int2 pr = reinterpret_cast<const int2*>(m.cft)[cf];
             tet = pr.x == w.cur ? pr.y : pr.x;
             if (tet < 0) return TM_RAY_INVALID;
+            w.cur = int32_t(field);   // the other tet's record holds this field for the face
         } else {
             tet = int32_t(field);
         }
         if (uint32_t(tet) >= uint32_t(m.nt)) return TM_RAY_STEP_CAP;
         w.next = uint32_t(tet);
         const int32_t a0 = w.a0, a1 = w.a1, a2 = w.a2;
-        walk_step<true>(M, uint32_t(m.nt), uint32_t(m.np), f, g, w);
-        if (w.next == kAbort) return TM_RAY_STEP_CAP;
+        walk_step<true, LAYOUT>(M, f, g, w);
+        w.cur = tet;
         // the vertex the new face dropped: the tet is {a0, a1, a2, id3}
         const int32_t x = (w.a0 != a0) ? a0 : ((w.a1 != a1) ? a1 : a2);
         // the segment leaves this tet through the new face at the depth of the
@@ -368,7 +420,7 @@ __device__ __forceinline__ void write_code(const RayArgs& r, int64_t i, int32_t 
 
 // Set-up of ray i.  Returns true when the ray needs walking (state in s);
 // false when its result is already written.
-template <bool TMAX>
+template <bool TMAX, int LAYOUT>
 __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, Ray& s) {
     const float ox = r.orig[3 * i], oy = r.orig[3 * i + 1], oz = r.orig[3 * i + 2];
     const float dx = r.dir[3 * i], dy = r.dir[3 * i + 1], dz = r.dir[3 * i + 2];
@@ -404,7 +456,7 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
         if (TMAX) { s.w.e0 = depth(s.g, PA); s.w.e1 = depth(s.g, PB); s.w.e2 = depth(s.g, PC); }
         make_ccw(s.w);
         s.w.next = uint32_t(start);
-        s.w.cur = -1;
+        s.w.cur = int32_t(0x80000000u | uint32_t(sf));   // the start tet's field for this face
         return true;
     }
     int32_t v[4];
@@ -416,13 +468,13 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
         const int4 sv = reinterpret_cast<const int4*>(m.tetv)[tet];
         v[0] = sv.x; v[1] = sv.y; v[2] = sv.z; v[3] = sv.w;
     } else {
-        tet = locate_point(m, M, ox, oy, oz, r.max_steps, v);
+        tet = locate_point<LAYOUT>(m, M, ox, oy, oz, r.max_steps, v);
         if (tet < 0) { write_code(r, i, tet, 0); return false; }
     }
     specialized_basis(dx, dy, dz, s.f);
     set_origin(s.f, ox, oy, oz);
     if (TMAX) set_depth(s.g, dx, dy, dz, ox, oy, oz);
-    const float sx = start_in_tet<TMAX>(M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w);
+    const float sx = start_in_tet<TMAX, LAYOUT>(m, M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w);
     if (!(sx < INFINITY)) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
     return true;
 }
@@ -450,7 +502,9 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
     }
     if (nx == kBoundary) { write_code(r, i, TM_RAY_MISS, s.steps); return; }
     const uint32_t cf = nx & kIdMask;
-    if (nx == kAbort || cf >= uint32_t(m.ntri)) { write_code(r, i, TM_RAY_STEP_CAP, s.steps); return; }
+    if (cf >= uint32_t(m.ntri)) { write_code(r, i, TM_RAY_STEP_CAP, s.steps); return; }
+    // reload the ray from memory rather than keeping it in registers through the walk
+    asm volatile("" ::: "memory");
     const int4 fv = reinterpret_cast<const int4*>(m.cfv)[cf];
     const float4 A = load_pt(M, uint32_t(fv.x)), B = load_pt(M, uint32_t(fv.y)),
                  C = load_pt(M, uint32_t(fv.z));
@@ -478,15 +532,18 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
 }
 
 // One lane per ray: set-up, walk, result.
-template <bool TMAX>
-__global__ void __launch_bounds__(256) k_trace(DevMesh m, RayArgs r) {
+// 8 waves per SIMD (at most 64 VGPRs): the walk is latency-bound, so occupancy
+// is what hides the memory round trips.
+template <bool TMAX, int LAYOUT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_trace(DevMesh m, RayArgs r) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= r.n) return;
-    const Mem M = make_mem(m);
+    const Mem M = make_mem<LAYOUT>(m);
     Ray s;
-    if (!setup_ray<TMAX>(m, M, r, i, s)) return;
+    if (!setup_ray<TMAX, LAYOUT>(m, M, r, i, s)) return;
     while (walk_on<TMAX>(s, r.max_steps)) {
-        walk_step<TMAX>(M, uint32_t(m.nt), uint32_t(m.np), s.f, s.g, s.w);
+        walk_step<TMAX, LAYOUT>(M, s.f, s.g, s.w);
         ++s.steps;
     }
     finish_ray<TMAX>(m, M, r, i, s);
@@ -497,12 +554,11 @@ __global__ void __launch_bounds__(256) k_trace(DevMesh m, RayArgs r) {
 // wave walks until `refill` of its lanes have finished, then writes those
 // results and sets up their next rays together, so the dependent loads of
 // set-up and result are paid once per batch rather than on every step.
-template <bool TMAX>
+template <bool TMAX, int LAYOUT>
 __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, int32_t refill) {
     const int64_t L = int64_t(gridDim.x) * blockDim.x;
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const Mem M = make_mem(m);
-    const uint32_t nt = uint32_t(m.nt), np = uint32_t(m.np);
+    const Mem M = make_mem<LAYOUT>(m);
     Ray s;
     bool has = false;   // the lane holds ray i
     bool done = false;  // ... and its walk has stopped
@@ -515,7 +571,7 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
         }
         if (!has) {
             while (i < r.n) {
-                if (setup_ray<TMAX>(m, M, r, i, s)) { has = true; break; }
+                if (setup_ray<TMAX, LAYOUT>(m, M, r, i, s)) { has = true; break; }
                 i += L;
             }
         }
@@ -525,29 +581,28 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
             done = has && !go;
             if (__popcll(__ballot(done)) >= uint32_t(refill) || !__any(go)) break;
             if (go) {
-                walk_step<TMAX>(M, nt, np, s.f, s.g, s.w);
+                walk_step<TMAX, LAYOUT>(M, s.f, s.g, s.w);
                 ++s.steps;
             }
         }
     }
 }
 
+template <int LAYOUT>
 __global__ void __launch_bounds__(256) k_locate(DevMesh m, int64_t n, const float* pts, int32_t* out,
                                                 int32_t max_steps) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const Mem M = make_mem(m);
+    const Mem M = make_mem<LAYOUT>(m);
     const float px = pts[3 * i], py = pts[3 * i + 1], pz = pts[3 * i + 2];
     if (!isfinite(px + py + pz)) { out[i] = -1; return; }
     int32_t v[4];
-    const int32_t t = locate_point(m, M, px, py, pz, max_steps, v);
+    const int32_t t = locate_point<LAYOUT>(m, M, px, py, pz, max_steps, v);
     out[i] = t >= 0 ? m.t_new2old[t] : (t == TM_RAY_STEP_CAP ? -2 : -1);
 }
 
-}  // namespace
-
-hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s) {
-    if (r.n <= 0) return hipSuccess;
+template <bool TMAX, int LAYOUT>
+void launch_trace_t(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s) {
     const int block = (c.block == 64 || c.block == 128) ? c.block : 256;
     const int64_t simple_grid = (r.n + block - 1) / block;
     if (c.kernel == 2) {
@@ -556,15 +611,23 @@ hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, 
         int64_t grid = std::min<int64_t>(simple_grid, std::max<int64_t>(1, c.cus * blocks_per_cu));
         if (c.grid_cap > 0) grid = std::min<int64_t>(grid, c.grid_cap);
         const int32_t refill = std::min(64, std::max(1, c.refill));
-        if (r.tmax)
-            hipLaunchKernelGGL(k_trace_persistent<true>, dim3(unsigned(grid)), dim3(block), 0, s, m, r, refill);
-        else
-            hipLaunchKernelGGL(k_trace_persistent<false>, dim3(unsigned(grid)), dim3(block), 0, s, m, r, refill);
+        hipLaunchKernelGGL((k_trace_persistent<TMAX, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s,
+                           m, r, refill);
     } else {
-        if (r.tmax)
-            hipLaunchKernelGGL(k_trace<true>, dim3(unsigned(simple_grid)), dim3(block), 0, s, m, r);
-        else
-            hipLaunchKernelGGL(k_trace<false>, dim3(unsigned(simple_grid)), dim3(block), 0, s, m, r);
+        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m, r);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s) {
+    if (r.n <= 0) return hipSuccess;
+    if (m.layout == kTet16) {
+        if (r.tmax) launch_trace_t<true, kTet16>(m, r, c, s);
+        else launch_trace_t<false, kTet16>(m, r, c, s);
+    } else {
+        if (r.tmax) launch_trace_t<true, kTet20>(m, r, c, s);
+        else launch_trace_t<false, kTet20>(m, r, c, s);
     }
     return hipGetLastError();
 }
@@ -574,7 +637,10 @@ hipError_t launch_locate(const DevMesh& m, int64_t n, const float* pts, int32_t*
     if (n <= 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (n + block - 1) / block;
-    hipLaunchKernelGGL(k_locate, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
+    if (m.layout == kTet16)
+        hipLaunchKernelGGL(k_locate<kTet16>, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
+    else
+        hipLaunchKernelGGL(k_locate<kTet20>, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
     return hipGetLastError();
 }
 

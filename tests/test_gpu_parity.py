@@ -29,9 +29,10 @@ def tetrt():
     return tetrt
 
 
-@pytest.fixture(scope="module")
-def tiny(tetrt, tiny_mesh, tiny_oracle):
-    mesh = tetrt.upload(tiny_mesh.points, tiny_mesh.tets, tiny_mesh.nbrs, tiny_mesh.cflag)
+@pytest.fixture(scope="module", params=["tet20", "tet16"])
+def tiny(request, tetrt, tiny_mesh, tiny_oracle):
+    mesh = tetrt.upload(tiny_mesh.points, tiny_mesh.tets, tiny_mesh.nbrs, tiny_mesh.cflag,
+                        layout=request.param)
     yield tiny_mesh, tiny_oracle, mesh
     mesh.free()
 
@@ -75,11 +76,12 @@ def test_tiny_ao(tiny, kw):
     assert np.array_equal(got["hit_tets"][same], ref["tets"][same])
 
 
+@pytest.mark.parametrize("layout", ["tet20", "tet16"])
 @pytest.mark.parametrize("n,seed", [(4, 1), (8, 2), (13, 3)])
-def test_random_rays_small_meshes(tetrt, n, seed):
+def test_random_rays_small_meshes(tetrt, n, seed, layout):
     m = kuhn_mesh(n, jitter=0.1, seed=seed, spheres=random_spheres(4, seed=seed, r_lo=0.1, r_hi=0.3))
     om = oracle.OracleMesh.from_kuhn(m)
-    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag)
+    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=layout)
     o, d = random_interior_rays(20000, seed)
     tm = np.random.default_rng(seed).uniform(0.05, 1.5, 20000).astype(np.float32)
     tm[::4] = np.inf
@@ -204,3 +206,18 @@ def test_persistent_matches_one_lane_per_ray(tiny, refill):
                          want_steps=True, kernel=2, grid_cap=3, refill=refill))
     for k in a:
         assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_layouts_agree(tetrt, tiny_mesh):
+    """Tet20 and Tet16 run the same arithmetic on the same geometry: identical
+    outputs (only the neighbour decoding differs)."""
+    m = tiny_mesh
+    o, d = random_interior_rays(30000, 41)
+    tm = np.random.default_rng(4).uniform(0.0, 0.8, 30000).astype(np.float32)
+    outs = []
+    for layout in ("tet20", "tet16"):
+        mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=layout)
+        outs.append(_host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), want_tets=True, want_steps=True)))
+        mesh.free()
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k], equal_nan=True), k
