@@ -102,6 +102,9 @@ typedef struct {
                             refill, 1..64 (0 = 16) */
     int32_t grid_cap;    /* persistent lanes: at most this many blocks (0 = enough blocks
                             to fill every compute unit) */
+    int32_t xcds;        /* one lane per ray: number of accelerator dies (XCDs) that get one
+                            contiguous range of blocks each; 1 = off, 0 = automatic (8 on
+                            a 256-CU MI355X) */
 } tm_trace_opts;
 
 /*

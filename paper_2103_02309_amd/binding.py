@@ -31,7 +31,7 @@ class _UploadOpts(C.Structure):
 
 class _TraceOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("block", C.c_int32), ("kernel", C.c_int32),
-                ("refill", C.c_int32), ("grid_cap", C.c_int32)]
+                ("refill", C.c_int32), ("grid_cap", C.c_int32), ("xcds", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -136,7 +136,7 @@ def tetmesh_upload(points, tets, nbrs, cflag, layout="tet20", sfc="hilbert", val
 
 def trace_closest(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, start_face=None,
                   hit_tets=None, steps=None, max_steps=0, block=0, kernel=0, refill=0, grid_cap=0,
-                  stream=None):
+                  xcds=0, stream=None):
     """Enqueue a trace of ``orig``/``dirs`` ([n, 3] float32, device) writing into the
     given device tensors; asynchronous on ``stream`` (default: the current one)."""
     n = int(orig.shape[0]) if orig.dim() >= 1 else 0
@@ -148,7 +148,7 @@ def trace_closest(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, s
             _dev(bary, torch.float32, n, (2,), "bary"),
             _dev(hit_tets, torch.int32, n, (2,), "hit_tets", True),
             _dev(steps, torch.int32, n, (), "steps", True)]
-    opts = _TraceOpts(int(max_steps), int(block), int(kernel), int(refill), int(grid_cap))
+    opts = _TraceOpts(int(max_steps), int(block), int(kernel), int(refill), int(grid_cap), int(xcds))
     _check(_load().trace_closest(C.c_void_p(handle), n, *args, C.byref(opts), _stream(stream)))
 
 
@@ -204,7 +204,8 @@ class Mesh:
             tetmesh_free(h)
 
     def trace(self, orig, dirs, tmax=None, start_tet=None, start_face=None, want_tets=False,
-              want_steps=False, max_steps=0, block=0, kernel=0, refill=0, grid_cap=0, stream=None):
+              want_steps=False, max_steps=0, block=0, kernel=0, refill=0, grid_cap=0, xcds=0,
+              stream=None):
         n = int(orig.shape[0])
         dev = orig.device
         out = {"tri": torch.empty(n, dtype=torch.int32, device=dev),
@@ -215,15 +216,15 @@ class Mesh:
         if want_steps:
             out["steps"] = torch.empty(n, dtype=torch.int32, device=dev)
         self.trace_into(out, orig, dirs, tmax, start_tet, start_face, max_steps, block, kernel,
-                        refill, grid_cap, stream)
+                        refill, grid_cap, xcds, stream)
         return out
 
     def trace_into(self, out, orig, dirs, tmax=None, start_tet=None, start_face=None, max_steps=0,
-                   block=0, kernel=0, refill=0, grid_cap=0, stream=None):
+                   block=0, kernel=0, refill=0, grid_cap=0, xcds=0, stream=None):
         trace_closest(self.handle, orig, dirs, out["tri"], out["t"], out["bary"], tmax=tmax,
                       start_tet=start_tet, start_face=start_face, hit_tets=out.get("hit_tets"),
                       steps=out.get("steps"), max_steps=max_steps, block=block, kernel=kernel,
-                      refill=refill, grid_cap=grid_cap, stream=stream)
+                      refill=refill, grid_cap=grid_cap, xcds=xcds, stream=stream)
         return out
 
     def locate(self, pts, stream=None):

@@ -166,7 +166,7 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
         return fail(TM_ERR_ARG, "trace_closest: NULL required array");
     if ((reinterpret_cast<uintptr_t>(d_bary) & 7) || (reinterpret_cast<uintptr_t>(d_hit_tets) & 7))
         return fail(TM_ERR_ARG, "trace_closest: bary / hit_tets must be 8-byte aligned");
-    tm_trace_opts o = {0, 0, 0, 0, 0};
+    tm_trace_opts o = {0, 0, 0, 0, 0, 0};
     if (opts) o = *opts;
     if (o.max_steps < 0) return fail(TM_ERR_ARG, "trace_closest: negative max_steps");
     if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
@@ -174,6 +174,7 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     if (o.kernel < 0 || o.kernel > 2) return fail(TM_ERR_ARG, "trace_closest: kernel must be 0, 1 or 2");
     if (o.refill < 0 || o.refill > 64) return fail(TM_ERR_ARG, "trace_closest: refill must be in [0, 64]");
     if (o.grid_cap < 0) return fail(TM_ERR_ARG, "trace_closest: negative grid_cap");
+    if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "trace_closest: xcds must be in [0, 64]");
     tetrt::RayArgs r;
     r.orig = d_orig;
     r.dir = d_dir;
@@ -193,6 +194,8 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     c.waves_per_simd = 8;
     c.refill = o.refill ? o.refill : 16;
     c.grid_cap = o.grid_cap;
+    // MI355X: 256 CUs in 8 XCDs of 32
+    c.xcds = o.xcds ? o.xcds : (m->cus % 32 == 0 && m->cus >= 256 ? m->cus / 32 : 1);
     // persistent lanes pay off once every lane gets several rays
     const int64_t lanes = int64_t(c.cus) * 4 * 64 * c.waves_per_simd;
     (void)lanes;

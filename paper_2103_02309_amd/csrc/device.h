@@ -52,6 +52,7 @@ struct LaunchCfg {
     int32_t waves_per_simd; // persistent: resident waves per SIMD to launch for
     int32_t cus;            // compute units of the device
     int32_t grid_cap;       // persistent: at most this many blocks (0 = no cap)
+    int32_t xcds;           // one lane per ray: XCDs to give contiguous block ranges (1 = off)
 };
 
 hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s);

@@ -534,10 +534,20 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
 // One lane per ray: set-up, walk, result.
 // 8 waves per SIMD (at most 64 VGPRs): the walk is latency-bound, so occupancy
 // is what hides the memory round trips.
+// The dispatcher deals blocks to the XCDs round-robin (block b runs on XCD
+// b mod X).  Renumbering so that each XCD gets one contiguous run of blocks
+// keeps neighbouring rays -- which visit the same tets -- on one L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t X) {
+    if (X <= 1) return b;
+    const uint32_t q = nb / X, rem = nb % X;
+    const uint32_t x = b % X, k = b / X;
+    return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+}
+
 template <bool TMAX, int LAYOUT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
-k_trace(DevMesh m, RayArgs r) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+k_trace(DevMesh m, RayArgs r, uint32_t xcds) {
+    const int64_t i = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds)) * blockDim.x + threadIdx.x;
     if (i >= r.n) return;
     const Mem M = make_mem<LAYOUT>(m);
     Ray s;
@@ -614,7 +624,8 @@ void launch_trace_t(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipS
         hipLaunchKernelGGL((k_trace_persistent<TMAX, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s,
                            m, r, refill);
     } else {
-        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m, r);
+        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m, r,
+                           uint32_t(std::max(1, c.xcds)));
     }
 }
 
