@@ -56,9 +56,12 @@ enum {
 enum {
     TM_LAYOUT_TET20 = 0, /* xor of the four vertex ids + four neighbour fields
                             ordered by the id of the vertex they face (20 B/tet) */
-    TM_LAYOUT_TET16 = 1  /* xor of the four vertex ids + three neighbour fields each
+    TM_LAYOUT_TET16 = 1, /* xor of the four vertex ids + three neighbour fields each
                             xored with the fourth; the walk decodes the next tet from
                             the previous one (16 B/tet) */
+    TM_LAYOUT_TET32N = 2 /* not a layout of the paper: the four neighbour fields + the
+                            xor-sum of each neighbour (32 B/tet), so a walk step loads
+                            its record and its point together */
 };
 
 /* memory order of points and tets (paper, Sec. "Reordering tetrahedral mesh data") */
@@ -103,8 +106,8 @@ typedef struct {
     int32_t grid_cap;    /* persistent lanes: at most this many blocks (0 = enough blocks
                             to fill every compute unit) */
     int32_t xcds;        /* one lane per ray: number of accelerator dies (XCDs) that get one
-                            contiguous range of blocks each; 1 = off, 0 = automatic (8 on
-                            a 256-CU MI355X) */
+                            contiguous range of blocks each; 0 or 1 = off (round-robin
+                            placement, which balances the dies) */
 } tm_trace_opts;
 
 /*
@@ -131,9 +134,9 @@ typedef struct {
  *                                      set on both sides of an interior face
  *   opts     host, nullable
  *   out      host; receives the handle (owns all device memory until tetmesh_free)
- * Limits: 1 <= n_tets <= 214,748,364 (20-byte records addressed by 32-bit byte
- * offsets), 4 <= n_points <= 268,435,455, fewer than 2^31 - 1 constrained
- * triangles.  Inputs are copied; the caller may free them on return.
+ * Limits: 1 <= n_tets <= 214,748,364 (134,217,727 with TM_LAYOUT_TET32N; records
+ * are addressed by 32-bit byte offsets), 4 <= n_points <= 268,435,455, fewer
+ * than 2^31 - 1 constrained triangles.  Inputs are copied; the caller may free them on return.
  * Errors: TM_ERR_ARG, TM_ERR_MESH (with validate = 1: vertex id out of range,
  * repeated vertex, zero volume, neighbour link not mutual, neighbours not
  * sharing the face, flag set on one side only -- the first offending tet is

@@ -14,7 +14,7 @@ _LIB_PATH = os.path.join(_HERE, "libtetrt.so")
 
 TM_OK, TM_ERR_ARG, TM_ERR_MESH, TM_ERR_OOM, TM_ERR_HIP = 0, -1, -2, -3, -4
 RAY_MISS, RAY_STEP_CAP, RAY_INVALID = -1, -2, -3
-_LAYOUTS = {"tet20": 0, "tet16": 1}
+_LAYOUTS = {"tet20": 0, "tet16": 1, "tet32n": 2}
 _SFC = {"hilbert": 0, "morton": 1, "none": 2}
 
 

@@ -86,12 +86,15 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
         return fail(TM_ERR_ARG, "tetmesh_upload: n_points = %lld out of range [4, 2^31)",
                     (long long)n_points);
     // the kernels address records and points with 32-bit byte offsets
-    if (n_tets * 20 > int64_t(0xFFFFFFFFLL) || n_points * 16 > int64_t(0xFFFFFFFFLL))
-        return fail(TM_ERR_ARG, "tetmesh_upload: mesh too large (at most %lld tets and %lld points)",
-                    (long long)(0xFFFFFFFFLL / 20), (long long)(0xFFFFFFFFLL / 16));
+    {
+        const int64_t rb = (opts && opts->layout == TM_LAYOUT_TET32N) ? 32 : 20;
+        if (n_tets * rb > int64_t(0xFFFFFFFFLL) || n_points * 16 > int64_t(0xFFFFFFFFLL))
+            return fail(TM_ERR_ARG, "tetmesh_upload: mesh too large (at most %lld tets and %lld points)",
+                        (long long)(0xFFFFFFFFLL / rb), (long long)(0xFFFFFFFFLL / 16));
+    }
     tm_upload_opts o = {TM_LAYOUT_TET20, TM_SFC_HILBERT, 1, 0};
     if (opts) o = *opts;
-    if (o.layout != TM_LAYOUT_TET20 && o.layout != TM_LAYOUT_TET16)
+    if (o.layout != TM_LAYOUT_TET20 && o.layout != TM_LAYOUT_TET16 && o.layout != TM_LAYOUT_TET32N)
         return fail(TM_ERR_ARG, "tetmesh_upload: unsupported layout %d", o.layout);
     if (o.sfc < TM_SFC_HILBERT || o.sfc > TM_SFC_NONE)
         return fail(TM_ERR_ARG, "tetmesh_upload: unknown sfc %d", o.sfc);
@@ -195,7 +198,9 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     c.refill = o.refill ? o.refill : 16;
     c.grid_cap = o.grid_cap;
     // MI355X: 256 CUs in 8 XCDs of 32
-    c.xcds = o.xcds ? o.xcds : (m->cus % 32 == 0 && m->cus >= 256 ? m->cus / 32 : 1);
+    // off by default: round-robin placement balances the XCDs, and walk lengths vary
+    // across an image, so contiguous ranges leave some XCDs idle at the end
+    c.xcds = o.xcds ? o.xcds : 1;
     // persistent lanes pay off once every lane gets several rays
     const int64_t lanes = int64_t(c.cus) * 4 * 64 * c.waves_per_simd;
     (void)lanes;

@@ -11,13 +11,14 @@ namespace tetrt {
 // kernels by value.  Vector-typed arrays are stored as their scalar base type
 // and reinterpreted in the kernels (int4 / float4 / int2, 16- or 8-byte aligned).
 struct DevMesh {
-    const int32_t* rec;       // [nt*5] Tet20 records (xor field, N0..N3) or
-                              // [nt*4] Tet16 records (xor field, NX0..NX2)
+    const int32_t* rec;       // [nt*5] Tet20 records (xor field, N0..N3),
+                              // [nt*4] Tet16 records (xor field, NX0..NX2) or
+                              // [nt*8] Tet32N records (N0..N3, neighbours' xor fields)
     const int32_t* n3;        // [nt]      Tet16 only: N3 of every tet (cold, for starts)
     const float* pts;         // [np*4]    float4 per point
     const int32_t* tetv;      // [nt*4]    ascending vertex ids (int4 per tet)
     const int32_t* cfv;       // [ntri*4]  constrained-face vertices (int4)
-    const int32_t* cft;       // [ntri*2]  constrained-face tets (int2)
+    const int32_t* cft;       // [ntri*4]  constrained-face tets and their xor fields (int4)
     const int32_t* t_new2old; // [nt]
     const int32_t* t_old2new; // [nt]
     const int32_t* seed;      // [G^3]

@@ -320,11 +320,20 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
         M.pts4[4 * i + 2] = s[2];
     }
 
-    // ---- tet records (Tet20 or Tet16) --------------------------------------
+    // ---- tet records (Tet20, Tet16 or Tet32N) ------------------------------
     const bool t16 = opts.layout == TM_LAYOUT_TET16;
-    M.rec.resize(size_t((t16 ? 4 : 5) * nt));
+    const bool t32n = opts.layout == TM_LAYOUT_TET32N;
+    M.rec.resize(size_t((t16 ? 4 : (t32n ? 8 : 5)) * nt));
     if (t16) M.n3.resize(size_t(nt));
     M.tetv.resize(size_t(4 * nt));
+    std::vector<int32_t> vx_of(nt);   // xor field of every (new) tet
+    parallel_for(nt, [&](int64_t b, int64_t e) {
+        for (int64_t tn = b; tn < e; ++tn) {
+            int64_t t = M.t_new2old[tn];
+            vx_of[tn] = p_old2new[tets[4 * t]] ^ p_old2new[tets[4 * t + 1]] ^ p_old2new[tets[4 * t + 2]] ^
+                        p_old2new[tets[4 * t + 3]];
+        }
+    });
     parallel_for(nt, [&](int64_t b, int64_t e) {
         for (int64_t tn = b; tn < e; ++tn) {
             int64_t t = M.t_new2old[tn];
@@ -339,21 +348,30 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
                     std::swap(slot[c], slot[c - 1]);
                 }
             uint32_t field[4];
+            int32_t nvx[4];
             for (int r = 0; r < 4; ++r) {
                 int64_t f = 4 * t + slot[r];
-                if (cflag[f])
+                nvx[r] = 0;
+                if (cflag[f]) {
                     field[r] = kConstrainedBit | uint32_t(face_tri[f]);
-                else if (nbrs[f] < 0)
+                } else if (nbrs[f] < 0) {
                     field[r] = kBoundaryField;
-                else
+                } else {
                     field[r] = uint32_t(M.t_old2new[nbrs[f]]);
+                    nvx[r] = vx_of[field[r]];
+                }
                 M.tetv[4 * tn + r] = v[r];
             }
-            const int32_t vx = v[0] ^ v[1] ^ v[2] ^ v[3];
+            const int32_t vx = vx_of[tn];
             if (t16) {
                 M.rec[4 * tn] = vx;
                 for (int r = 0; r < 3; ++r) M.rec[4 * tn + 1 + r] = int32_t(field[r] ^ field[3]);
                 M.n3[tn] = int32_t(field[3]);
+            } else if (t32n) {
+                for (int r = 0; r < 4; ++r) {
+                    M.rec[8 * tn + r] = int32_t(field[r]);
+                    M.rec[8 * tn + 4 + r] = nvx[r];
+                }
             } else {
                 M.rec[5 * tn] = vx;
                 for (int r = 0; r < 4; ++r) M.rec[5 * tn + 1 + r] = int32_t(field[r]);
@@ -363,7 +381,7 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
 
     // ---- constrained-face table --------------------------------------------
     M.cfv.assign(size_t(4 * ntri), 0);
-    M.cft.assign(size_t(2 * ntri), -1);
+    M.cft.assign(size_t(4 * ntri), -1);
     for (int64_t f = 0; f < ntri; ++f) {
         const int32_t* u = &M.tri_verts_user[3 * f];
         for (int k = 0; k < 3; ++k) M.cfv[4 * f + k] = p_old2new[u[k]];
@@ -386,8 +404,11 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
         double side = n[0] * (double(W[0]) - A[0]) + n[1] * (double(W[1]) - A[1]) +
                       n[2] * (double(W[2]) - A[2]);
         int32_t na = M.t_old2new[ta], nbn = tb >= 0 ? M.t_old2new[tb] : -1;
-        M.cft[2 * f] = side > 0 ? na : nbn;
-        M.cft[2 * f + 1] = side > 0 ? nbn : na;
+        const int32_t pos = side > 0 ? na : nbn, neg = side > 0 ? nbn : na;
+        M.cft[4 * f] = pos;
+        M.cft[4 * f + 1] = neg;
+        M.cft[4 * f + 2] = pos >= 0 ? vx_of[pos] : 0;
+        M.cft[4 * f + 3] = neg >= 0 ? vx_of[neg] : 0;
     }
 
     // ---- seed grid for point location --------------------------------------

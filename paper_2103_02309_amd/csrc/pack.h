@@ -19,13 +19,16 @@ struct PackedMesh {
     std::vector<float> pts4;             // [np*4]   x, y, z, 0 in internal point order
     std::vector<int32_t> rec;            // Tet20 [nt*5]: xor of the four internal vertex ids, then
                                          //   the neighbour fields N0..N3 by ascending vertex id;
-                                         // Tet16 [nt*4]: xor, then NX_j = N_j ^ N_3 for j < 3
+                                         // Tet16 [nt*4]: xor, then NX_j = N_j ^ N_3 for j < 3;
+                                         // Tet32N [nt*8]: N0..N3, then each neighbour's xor
+                                         //   (0 where the field is not a tet)
     std::vector<int32_t> n3;             // Tet16 only [nt]: N_3 (cold, to start walks)
     std::vector<int32_t> tetv;           // [nt*4]   internal vertex ids, ascending (cold)
     std::vector<int32_t> cfv;            // [ntri*4] internal ids of the triangle's vertices in
                                          //          ascending caller-id order, then 0
-    std::vector<int32_t> cft;            // [ntri*2] internal tet on the + side of
-                                         //          (v1-v0)x(v2-v0), then the - side (-1 = none)
+    std::vector<int32_t> cft;            // [ntri*4] internal tet on the + side of
+                                         //          (v1-v0)x(v2-v0), the - side (-1 = none),
+                                         //          then the xor fields of those two tets
     std::vector<int32_t> t_new2old;      // [nt]
     std::vector<int32_t> t_old2new;      // [nt]
     std::vector<int32_t> tri_verts_user; // [ntri*3] caller vertex ids, ascending

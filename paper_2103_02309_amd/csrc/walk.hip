@@ -29,8 +29,15 @@
 //          entry face (known: it refers back to the previous tet) xor NX of the
 //          entry vertex's rank xor NX of the exit vertex's rank (NX_3 = 0),
 //          Algorithms 6-7.
-// The point is one 16-byte load, so a step is two dependent round trips
-// (record, then point).  Buffer loads return zero beyond the array instead of
+// With these the point is one 16-byte load after the record, so a step is
+// two dependent round trips (record, then point).
+//   Tet32N 32 bytes {N0..N3, W0..W3}: the neighbour fields and each
+//          neighbour's xor-sum.  The xor-sum of the tet being entered comes
+//          with the previous record, so the record and the point of a step are
+//          loaded together: one round trip per step, for twice the bytes of
+//          Tet16.  Not one of the paper's layouts: the paper's xor idea moved
+//          one step ahead, because on gfx950 the walk is bound by the latency of
+//          dependent loads rather than by bytes.  Buffer loads return zero beyond the array instead of
 // faulting, and the step is branch-free: the loop test is its only branch.
 #include <hip/hip_runtime.h>
 
@@ -50,9 +57,10 @@ constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 // record layouts
 constexpr int kTet20 = 0;
 constexpr int kTet16 = 1;
+constexpr int kTet32N = 2;
 
 template <int LAYOUT>
-constexpr uint32_t rec_bytes() { return LAYOUT == kTet20 ? 20u : 16u; }
+constexpr uint32_t rec_bytes() { return LAYOUT == kTet20 ? 20u : (LAYOUT == kTet16 ? 16u : 32u); }
 
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
@@ -81,10 +89,12 @@ __device__ __forceinline__ Mem make_mem(const DevMesh& m) {
 __device__ __forceinline__ void keep(uint32_t& v) { asm volatile("" : "+v"(v)); }
 
 // A record as loaded: the xor field and four more words (Tet20: N0..N3 by
-// ascending vertex id; Tet16: NX0..NX2 and 0).
+// ascending vertex id; Tet16: NX0..NX2 and 0; Tet32N: N0..N3 and the
+// neighbours' xor-sums w0..w3, no xor field of its own).
 struct Rec {
     int32_t vx;
     uint32_t n0, n1, n2, n3;
+    uint32_t w0, w1, w2, w3;
 };
 
 template <int LAYOUT>
@@ -96,10 +106,14 @@ __device__ __forceinline__ Rec load_rec(const Mem& M, uint32_t tet) {
         const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, off, 0, 0);
         uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(M.rec, off + 16u, 0, 0);
         keep(b);
-        return Rec{int32_t(a[0]), a[1], a[2], a[3], b};
-    } else {
+        return Rec{int32_t(a[0]), a[1], a[2], a[3], b, 0u, 0u, 0u, 0u};
+    } else if (LAYOUT == kTet16) {
         const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, tet << 4, 0, 0);
-        return Rec{int32_t(a[0]), a[1], a[2], a[3], 0u};
+        return Rec{int32_t(a[0]), a[1], a[2], a[3], 0u, 0u, 0u, 0u, 0u};
+    } else {
+        const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, tet << 5, 0, 0);
+        const auto b = __builtin_amdgcn_raw_buffer_load_b128(M.rec, (tet << 5) + 16u, 0, 0);
+        return Rec{0, a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
     }
 }
 
@@ -117,10 +131,10 @@ __device__ __forceinline__ uint32_t pick4(uint32_t w0, uint32_t w1, uint32_t w2,
 
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t next_field(const Rec& R, int r, uint32_t back, int ra) {
-    if (LAYOUT == kTet20) {
-        return pick4(R.n0, R.n1, R.n2, R.n3, r);
-    } else {
+    if (LAYOUT == kTet16) {
         return back ^ pick4(R.n0, R.n1, R.n2, 0u, ra) ^ pick4(R.n0, R.n1, R.n2, 0u, r);
+    } else {
+        return pick4(R.n0, R.n1, R.n2, R.n3, r);
     }
 }
 
@@ -221,6 +235,7 @@ struct Walk {
     float e0, e1, e2;
     uint32_t next;
     int32_t cur;
+    int32_t vxn;   // Tet32N: xor-sum of the tet `next` refers to
 };
 
 __device__ __forceinline__ void make_ccw(Walk& w) {
@@ -239,7 +254,7 @@ template <bool DEPTH, int LAYOUT>
 __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const Depth& g, Walk& w) {
     const uint32_t tet = w.next;
     const Rec R = load_rec<LAYOUT>(M, tet);
-    const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ R.vx;
+    const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ (LAYOUT == kTet32N ? w.vxn : R.vx);
     const float4 P = load_pt(M, uint32_t(id3));
     float q3x, q3y;
     project(f, P, q3x, q3y);
@@ -249,6 +264,7 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
     const int r = (w.a0 < x) + (w.a1 < x) + (w.a2 < x) + (id3 < x);
     const int ra = LAYOUT == kTet16 ? (w.a0 < id3) + (w.a1 < id3) + (w.a2 < id3) : 0;
     w.next = next_field<LAYOUT>(R, r, uint32_t(w.cur), ra);
+    if (LAYOUT == kTet32N) w.vxn = int32_t(pick4(R.w0, R.w1, R.w2, R.w3, r));
     w.cur = int32_t(tet);
     const bool s2 = !(s0 | s1);
     w.a0 = s0 ? id3 : w.a0;  w.q0x = s0 ? q3x : w.q0x;  w.q0y = s0 ? q3y : w.q0y;
@@ -318,8 +334,9 @@ __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const
     const int r = (v[0] < x) + (v[1] < x) + (v[2] < x) + (v[3] < x);
     const Rec R = load_rec<LAYOUT>(M, uint32_t(tet));
     // Tet16 keeps N3 of every tet in a cold array for starts: N_r = N3 ^ NX_r
-    w.next = LAYOUT == kTet20 ? next_field<kTet20>(R, r, 0u, 0)
-                              : next_field<kTet16>(R, r, uint32_t(m.n3[tet]), 3);
+    w.next = LAYOUT == kTet16 ? next_field<kTet16>(R, r, uint32_t(m.n3[tet]), 3)
+                              : next_field<kTet20>(R, r, 0u, 0);
+    if (LAYOUT == kTet32N) w.vxn = int32_t(pick4(R.w0, R.w1, R.w2, R.w3, r));
     w.cur = tet;
     make_ccw(w);
     return best;
@@ -367,10 +384,12 @@ __device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float 
         if (field & 0x80000000u) {
             const uint32_t cf = field & kIdMask;
             if (cf >= uint32_t(m.ntri)) return TM_RAY_STEP_CAP;
-            const int2 pr = reinterpret_cast<const int2*>(m.cft)[cf];
-            tet = pr.x == w.cur ? pr.y : pr.x;
+            const int4 pr = reinterpret_cast<const int4*>(m.cft)[cf];
+            const bool other_neg = pr.x == w.cur;
+            tet = other_neg ? pr.y : pr.x;
             if (tet < 0) return TM_RAY_INVALID;
             w.cur = int32_t(field);   // the other tet's record holds this field for the face
+            w.vxn = other_neg ? pr.w : pr.z;
         } else {
             tet = int32_t(field);
         }
@@ -436,7 +455,7 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
         // secondary ray: start in the tet on the side of the face that dir points into
         if (sf >= m.ntri) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
         const int4 fv = reinterpret_cast<const int4*>(m.cfv)[sf];
-        const int2 ft = reinterpret_cast<const int2*>(m.cft)[sf];
+        const int4 ft = reinterpret_cast<const int4*>(m.cft)[sf];
         const float4 PA = load_pt(M, uint32_t(fv.x)), PB = load_pt(M, uint32_t(fv.y)),
                      PC = load_pt(M, uint32_t(fv.z));
         const float e1x = PB.x - PA.x, e1y = PB.y - PA.y, e1z = PB.z - PA.z;
@@ -445,6 +464,7 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
                          (e1x * e2y - e1y * e2x) * dz;
         if (nd == 0.0f) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
         const int32_t start = nd > 0.0f ? ft.x : ft.y;
+        s.w.vxn = nd > 0.0f ? ft.z : ft.w;
         if (start < 0) { write_code(r, i, TM_RAY_MISS, 0); return false; }
         specialized_basis(dx, dy, dz, s.f);
         set_origin(s.f, ox, oy, oz);
@@ -523,7 +543,7 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
     if (TMAX && th > double(s.tmax)) { write_code(r, i, TM_RAY_MISS, s.steps); return; }
     int32_t front = -1, back = -1;
     if (r.hit_tets) {
-        const int2 ft = reinterpret_cast<const int2*>(m.cft)[cf];
+        const int4 ft = reinterpret_cast<const int4*>(m.cft)[cf];
         const int32_t other = ft.x == s.w.cur ? ft.y : ft.x;
         front = m.t_new2old[s.w.cur];
         back = other >= 0 ? m.t_new2old[other] : -1;
@@ -636,6 +656,9 @@ hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, 
     if (m.layout == kTet16) {
         if (r.tmax) launch_trace_t<true, kTet16>(m, r, c, s);
         else launch_trace_t<false, kTet16>(m, r, c, s);
+    } else if (m.layout == kTet32N) {
+        if (r.tmax) launch_trace_t<true, kTet32N>(m, r, c, s);
+        else launch_trace_t<false, kTet32N>(m, r, c, s);
     } else {
         if (r.tmax) launch_trace_t<true, kTet20>(m, r, c, s);
         else launch_trace_t<false, kTet20>(m, r, c, s);
@@ -650,6 +673,8 @@ hipError_t launch_locate(const DevMesh& m, int64_t n, const float* pts, int32_t*
     const int64_t grid = (n + block - 1) / block;
     if (m.layout == kTet16)
         hipLaunchKernelGGL(k_locate<kTet16>, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
+    else if (m.layout == kTet32N)
+        hipLaunchKernelGGL(k_locate<kTet32N>, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
     else
         hipLaunchKernelGGL(k_locate<kTet20>, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
     return hipGetLastError();

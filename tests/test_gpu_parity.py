@@ -29,7 +29,10 @@ def tetrt():
     return tetrt
 
 
-@pytest.fixture(scope="module", params=["tet20", "tet16"])
+LAYOUTS = ["tet20", "tet16", "tet32n"]
+
+
+@pytest.fixture(scope="module", params=LAYOUTS)
 def tiny(request, tetrt, tiny_mesh, tiny_oracle):
     mesh = tetrt.upload(tiny_mesh.points, tiny_mesh.tets, tiny_mesh.nbrs, tiny_mesh.cflag,
                         layout=request.param)
@@ -76,7 +79,7 @@ def test_tiny_ao(tiny, kw):
     assert np.array_equal(got["hit_tets"][same], ref["tets"][same])
 
 
-@pytest.mark.parametrize("layout", ["tet20", "tet16"])
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("n,seed", [(4, 1), (8, 2), (13, 3)])
 def test_random_rays_small_meshes(tetrt, n, seed, layout):
     m = kuhn_mesh(n, jitter=0.1, seed=seed, spheres=random_spheres(4, seed=seed, r_lo=0.1, r_hi=0.3))
@@ -209,15 +212,16 @@ def test_persistent_matches_one_lane_per_ray(tiny, refill):
 
 
 def test_layouts_agree(tetrt, tiny_mesh):
-    """Tet20 and Tet16 run the same arithmetic on the same geometry: identical
+    """All layouts run the same arithmetic on the same geometry: identical
     outputs (only the neighbour decoding differs)."""
     m = tiny_mesh
     o, d = random_interior_rays(30000, 41)
     tm = np.random.default_rng(4).uniform(0.0, 0.8, 30000).astype(np.float32)
     outs = []
-    for layout in ("tet20", "tet16"):
+    for layout in LAYOUTS:
         mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=layout)
         outs.append(_host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), want_tets=True, want_steps=True)))
         mesh.free()
-    for k in outs[0]:
-        assert np.array_equal(outs[0][k], outs[1][k], equal_nan=True), k
+    for other in outs[1:]:
+        for k in outs[0]:
+            assert np.array_equal(outs[0][k], other[k], equal_nan=True), k
