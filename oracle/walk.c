@@ -32,9 +32,14 @@
  * Conventions that the paper leaves open (canonical triangle ids, tmax, error
  * codes, the start-face rule for secondary rays) are stated at each function.
  *
- * Per-ray result codes in out_tri: >= 0 triangle id, -1 miss, -2 step cap
- * reached, -3 invalid ray or origin outside the mesh, -4 the mesh violated the
- * face-connected chain invariant during the walk.
+ * Per-ray result codes in out_tri: >= 0 triangle id, -1 miss, -3 invalid ray
+ * or origin outside the mesh, -4 the mesh violated the face-connected chain
+ * invariant during the walk.  A straight line enters each tet at most once, so
+ * a walk longer than T steps can only be circling on a degenerate ray (one
+ * running along a tet edge, whose endpoints both project onto the 2-D origin
+ * and leave Algorithm 1 with zero determinants); such a ray takes the plain
+ * definition instead -- the closest of all constrained triangles it meets
+ * (Moller-Trumbore, inclusive edges) -- and reports steps = -1.
  *
  * Build: cc -O2 -ffp-contract=off -fPIC -shared walk.c -o liboracle.so -lm
  */
@@ -273,6 +278,57 @@ int oracle_locate(void* h, int64_t n, const float* xyz, int32_t source_tet, int3
     return 0;
 }
 
+/* ---- the definition: closest hit over all constrained triangles ---------- */
+
+/* Moller-Trumbore with inclusive edges over every triangle; t in (0, tmax],
+ * the start face excluded; ties within 1e-12 go to the lowest id.  Returns the
+ * id or -1 and fills t, the weights of the 2nd and 3rd vertex (ascending ids),
+ * and the tets in front of / behind the face along the ray. */
+static int32_t closest_by_definition(const omesh* m, const frame* F, double tm, int32_t exclude,
+                                     double* t_out, double bary[2], int32_t tets2[2]) {
+    int32_t best = -1;
+    double bt = INFINITY, bu = NAN, bv = NAN;
+    for (int64_t f = 0; f < m->ntri; ++f) {
+        if (f == exclude) continue;
+        const int32_t* tv = &m->tri_verts[3 * f];
+        v3 A = point(m, tv[0]), B = point(m, tv[1]), C = point(m, tv[2]);
+        v3 e1 = vsub(B, A), e2 = vsub(C, A);
+        v3 pv = vcross(F->d, e2);
+        double det = vdot(e1, pv);
+        if (det == 0.0) continue;
+        v3 sv = vsub(F->o, A);
+        double u = vdot(sv, pv) / det;
+        v3 qv = vcross(sv, e1);
+        double v = vdot(F->d, qv) / det;
+        double t = vdot(e2, qv) / det;
+        if (u < 0.0 || v < 0.0 || u + v > 1.0 || !(t > 0.0) || t > tm) continue;
+        if (t < bt - 1e-12 || (fabs(t - bt) <= 1e-12 && f < best)) {
+            if (t < bt) bt = t;
+            best = (int32_t)f; bu = u; bv = v;
+        }
+    }
+    tets2[0] = tets2[1] = -1;
+    if (best >= 0) {
+        /* the ray goes from the tet on one side of the face to the other */
+        const int32_t* tv = &m->tri_verts[3 * (int64_t)best];
+        v3 A = point(m, tv[0]);
+        v3 nf = vcross(vsub(point(m, tv[1]), A), vsub(point(m, tv[2]), A));
+        int32_t ta = m->tri_tets[2 * (int64_t)best], tb = m->tri_tets[2 * (int64_t)best + 1];
+        int32_t w = -1;
+        for (int s = 0; s < 4; ++s) {
+            int32_t x = m->tets[4 * (int64_t)ta + s];
+            if (x != tv[0] && x != tv[1] && x != tv[2]) w = x;
+        }
+        int ta_ahead = (vdot(nf, vsub(point(m, w), A)) > 0.0) == (vdot(nf, F->d) > 0.0);
+        tets2[0] = ta_ahead ? tb : ta;
+        tets2[1] = ta_ahead ? ta : tb;
+    }
+    *t_out = bt;
+    bary[0] = bu;
+    bary[1] = bv;
+    return best;
+}
+
 /* ---- the walk ------------------------------------------------------------ */
 
 /* Trace n rays.  Per ray i:
@@ -298,7 +354,7 @@ int oracle_trace(void* h, int64_t n, const float* orig, const float* dir, const 
                  int32_t* out_tets, int32_t* out_steps, int32_t* out_start) {
     omesh* m = (omesh*)h;
     if (source_tet < 0 || source_tet >= m->nt) return -1;
-    if (max_steps <= 0) max_steps = 4 * m->nt + 4;
+    if (max_steps <= 0) max_steps = m->nt + 4;
     for (int64_t i = 0; i < n; ++i) {
         frame F;
         F.o.x = orig[3 * i]; F.o.y = orig[3 * i + 1]; F.o.z = orig[3 * i + 2];
@@ -380,7 +436,11 @@ int oracle_trace(void* h, int64_t n, const float* orig, const float* dir, const 
                 if (d2 < dmin) dmin = d2;
                 if (dmin > tm) { code = -1; break; }
             }
-            if (steps >= max_steps) { code = -2; break; }
+            if (steps >= max_steps) {
+                code = closest_by_definition(m, &F, tm, sf, &tt, bary, tets2);
+                steps = -1;
+                goto done;
+            }
             ++steps;
             int32_t tet = nxt;
             /* the vertex of tet that is not on the face just crossed */
