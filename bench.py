@@ -28,7 +28,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
-STEP_BYTES = 20                # Tet20 walk step: xor field 4 B + one neighbour field 4 B + point 12 B
+# algorithmic bytes of one walk step: the fields the step needs, whatever the layout --
+# the xor field (4 B), one neighbour field (4 B) and the new point (12 B)
+STEP_BYTES = 20
 RAY_IO_BYTES = 24 + 16         # origin + direction in, tri + t + bary out
 OPT_INPUT_BYTES = 4            # per optional per-ray input (tmax, start face, start tet)
 
@@ -41,6 +43,7 @@ def parse():
     ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
     ap.add_argument("--tile", type=int, default=8, help="pixel tile edge for ray order (1 = row-major)")
     ap.add_argument("--sfc", default="hilbert", choices=["hilbert", "morton", "none"])
+    ap.add_argument("--layout", default="tet16", choices=["tet20", "tet16", "tet32n"])
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 one lane per ray, 2 persistent")
     ap.add_argument("--refill", type=int, default=0, help="persistent refill threshold (0 = default)")
@@ -83,7 +86,7 @@ def main():
     m, eye, W, H = workload(args.workload)
     log("mesh: %d tets, %d points (%.1f s)" % (m.n_tets, m.n_points, time.time() - t0))
     t0 = time.time()
-    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, sfc=args.sfc)
+    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, sfc=args.sfc, layout=args.layout)
     torch.cuda.synchronize()
     upload_s = time.time() - t0
     info = mesh.info
@@ -190,7 +193,7 @@ def main():
             "tets": m.n_tets, "points": m.n_points, "triangles": info["n_tris"],
             "primary_rays": n_p, "ao_rays": n_a, "ray_order": "8x8 tiles" if args.tile == 8 else
             ("row-major" if args.tile <= 1 else "%dx%d tiles" % (args.tile, args.tile)),
-            "layout": "tet20", "sfc": args.sfc, "block": args.block,
+            "layout": args.layout, "sfc": args.sfc, "block": args.block,
             "kernel": {0: "auto", 1: "one lane per ray", 2: "persistent lanes"}[args.kernel],
         },
         "roofline": {
