@@ -108,6 +108,19 @@ typedef struct {
     int32_t xcds;        /* one lane per ray: number of accelerator dies (XCDs) that get one
                             contiguous range of blocks each; 0 or 1 = off (round-robin
                             placement, which balances the dies) */
+    int32_t sort;        /* ray binning before the walk: 0 = automatic (on for batches of at
+                            least 2^18 rays that carry tmax), 1 = off, 2 = on.  Binned rays
+                            are grouped by origin cell (Morton order of a 2^k grid over the
+                            mesh bounds), then by direction, and traced in that order; the
+                            outputs stay at the caller's positions */
+    int32_t sort_cells_log2; /* k above, 1..7 (0 = 5: 32^3 cells) */
+    int32_t sort_dirq;   /* direction bins per axis, 1..8 (0 = 4) */
+    float eps;           /* reserved, must be 0 */
+    void* workspace;     /* device scratch for binning, or NULL: the handle then uses (and
+                            grows) a workspace of its own, so binned traces on one handle
+                            must not overlap in time unless each passes its own */
+    int64_t workspace_bytes; /* size of workspace (tetmesh_trace_workspace gives the need) */
+    int32_t* fp64_steps; /* reserved, must be NULL */
 } tm_trace_opts;
 
 /*
@@ -200,6 +213,12 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
  *   edge or vertex gets one of the tets that contain it.
  */
 int tetmesh_locate(tm_mesh m, int64_t n, const float* d_pts, int32_t* d_tet, void* hip_stream);
+
+/* tetmesh_trace_workspace -- bytes of device workspace a trace_closest call with
+ * these arguments needs (0 when it bins no rays).  d_tmax_present: the d_tmax
+ * argument of that call (only tested for NULL).  *bytes host out. */
+int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_present,
+                            const tm_trace_opts* opts, int64_t* bytes);
 
 /* tetmesh_tri_vertices -- host: vertex ids (caller numbering, ascending) of
  * triangles.  tri host int32 [n]; out host int32 [n][3].  TM_ERR_ARG on an id

@@ -8,8 +8,8 @@ PyTorch supplies device memory and the current stream.
 """
 from .binding import (TetRTError, Mesh, upload, tetmesh_upload, trace_closest, tetmesh_locate,
                       tetmesh_tri_vertices, tetmesh_info, tetmesh_free, tm_last_error,
-                      tetrt_sfc_keys, library_path, RAY_MISS, RAY_STEP_CAP, RAY_INVALID)
+                      tetrt_sfc_keys, tetmesh_trace_workspace, library_path, RAY_MISS, RAY_STEP_CAP, RAY_INVALID)
 
 __all__ = ["TetRTError", "Mesh", "upload", "tetmesh_upload", "trace_closest", "tetmesh_locate",
            "tetmesh_tri_vertices", "tetmesh_info", "tetmesh_free", "tm_last_error",
-           "tetrt_sfc_keys", "library_path", "RAY_MISS", "RAY_STEP_CAP", "RAY_INVALID"]
+           "tetrt_sfc_keys", "tetmesh_trace_workspace", "library_path", "RAY_MISS", "RAY_STEP_CAP", "RAY_INVALID"]

@@ -31,7 +31,27 @@ class _UploadOpts(C.Structure):
 
 class _TraceOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("block", C.c_int32), ("kernel", C.c_int32),
-                ("refill", C.c_int32), ("grid_cap", C.c_int32), ("xcds", C.c_int32)]
+                ("refill", C.c_int32), ("grid_cap", C.c_int32), ("xcds", C.c_int32),
+                ("sort", C.c_int32), ("sort_cells_log2", C.c_int32), ("sort_dirq", C.c_int32),
+                ("eps", C.c_float), ("workspace", C.c_void_p), ("workspace_bytes", C.c_int64),
+                ("fp64_steps", C.c_void_p)]
+
+_TRACE_KEYS = ("max_steps", "block", "kernel", "refill", "grid_cap", "xcds", "sort",
+               "sort_cells_log2", "sort_dirq")
+
+
+def _trace_opts(kw, workspace=None):
+    o = _TraceOpts()
+    for k in _TRACE_KEYS:
+        setattr(o, k, int(kw.pop(k, 0)))
+    if kw:
+        raise TypeError("unknown trace options: %s" % ", ".join(sorted(kw)))
+    if workspace is not None:
+        if not isinstance(workspace, torch.Tensor) or workspace.device.type != "cuda":
+            raise TypeError("workspace must be a HIP device tensor")
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    return o
 
 
 class _Info(C.Structure):
@@ -63,6 +83,8 @@ def _load():
     L.trace_closest.restype = C.c_int
     L.trace_closest.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                 C.POINTER(_TraceOpts), vp]
+    L.tetmesh_trace_workspace.restype = C.c_int
+    L.tetmesh_trace_workspace.argtypes = [vp, i64, vp, C.POINTER(_TraceOpts), C.POINTER(i64)]
     L.tetmesh_locate.restype = C.c_int
     L.tetmesh_locate.argtypes = [vp, i64, vp, vp, vp]
     L.tetmesh_tri_vertices.restype = C.c_int
@@ -135,10 +157,11 @@ def tetmesh_upload(points, tets, nbrs, cflag, layout="tet20", sfc="hilbert", val
 
 
 def trace_closest(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, start_face=None,
-                  hit_tets=None, steps=None, max_steps=0, block=0, kernel=0, refill=0, grid_cap=0,
-                  xcds=0, stream=None):
+                  hit_tets=None, steps=None, workspace=None, stream=None, **opts):
     """Enqueue a trace of ``orig``/``dirs`` ([n, 3] float32, device) writing into the
-    given device tensors; asynchronous on ``stream`` (default: the current one)."""
+    given device tensors; asynchronous on ``stream`` (default: the current one).
+    ``opts``: the tm_trace_opts fields (max_steps, block, kernel, refill, grid_cap,
+    xcds, sort, sort_cells_log2, sort_dirq)."""
     n = int(orig.shape[0]) if orig.dim() >= 1 else 0
     args = [_dev(orig, torch.float32, n, (3,), "orig"), _dev(dirs, torch.float32, n, (3,), "dirs"),
             _dev(tmax, torch.float32, n, (), "tmax", True),
@@ -148,8 +171,17 @@ def trace_closest(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, s
             _dev(bary, torch.float32, n, (2,), "bary"),
             _dev(hit_tets, torch.int32, n, (2,), "hit_tets", True),
             _dev(steps, torch.int32, n, (), "steps", True)]
-    opts = _TraceOpts(int(max_steps), int(block), int(kernel), int(refill), int(grid_cap), int(xcds))
-    _check(_load().trace_closest(C.c_void_p(handle), n, *args, C.byref(opts), _stream(stream)))
+    o = _trace_opts(dict(opts), workspace)
+    _check(_load().trace_closest(C.c_void_p(handle), n, *args, C.byref(o), _stream(stream)))
+
+
+def tetmesh_trace_workspace(handle, n_rays, has_tmax, **opts):
+    o = _trace_opts(dict(opts))
+    b = C.c_int64()
+    _check(_load().tetmesh_trace_workspace(C.c_void_p(handle), int(n_rays),
+                                           C.c_void_p(1 if has_tmax else 0), C.byref(o),
+                                           C.byref(b)))
+    return b.value
 
 
 def tetmesh_locate(handle, pts, out, stream=None):
@@ -204,8 +236,7 @@ class Mesh:
             tetmesh_free(h)
 
     def trace(self, orig, dirs, tmax=None, start_tet=None, start_face=None, want_tets=False,
-              want_steps=False, max_steps=0, block=0, kernel=0, refill=0, grid_cap=0, xcds=0,
-              stream=None):
+              want_steps=False, workspace=None, stream=None, **opts):
         n = int(orig.shape[0])
         dev = orig.device
         out = {"tri": torch.empty(n, dtype=torch.int32, device=dev),
@@ -215,17 +246,18 @@ class Mesh:
             out["hit_tets"] = torch.empty((n, 2), dtype=torch.int32, device=dev)
         if want_steps:
             out["steps"] = torch.empty(n, dtype=torch.int32, device=dev)
-        self.trace_into(out, orig, dirs, tmax, start_tet, start_face, max_steps, block, kernel,
-                        refill, grid_cap, xcds, stream)
+        self.trace_into(out, orig, dirs, tmax, start_tet, start_face, workspace, stream, **opts)
         return out
 
-    def trace_into(self, out, orig, dirs, tmax=None, start_tet=None, start_face=None, max_steps=0,
-                   block=0, kernel=0, refill=0, grid_cap=0, xcds=0, stream=None):
+    def trace_into(self, out, orig, dirs, tmax=None, start_tet=None, start_face=None,
+                   workspace=None, stream=None, **opts):
         trace_closest(self.handle, orig, dirs, out["tri"], out["t"], out["bary"], tmax=tmax,
                       start_tet=start_tet, start_face=start_face, hit_tets=out.get("hit_tets"),
-                      steps=out.get("steps"), max_steps=max_steps, block=block, kernel=kernel,
-                      refill=refill, grid_cap=grid_cap, xcds=xcds, stream=stream)
+                      steps=out.get("steps"), workspace=workspace, stream=stream, **opts)
         return out
+
+    def workspace_bytes(self, n_rays, has_tmax, **opts):
+        return tetmesh_trace_workspace(self.handle, n_rays, has_tmax, **opts)
 
     def locate(self, pts, stream=None):
         out = torch.empty(int(pts.shape[0]), dtype=torch.int32, device=pts.device)

@@ -1,9 +1,11 @@
 // C-ABI entry points declared in include/tetrt.h.
 #include <hip/hip_runtime_api.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -21,6 +23,10 @@ struct tm_mesh_s {
     int64_t hot_bytes = 0, cold_bytes = 0;
     std::vector<int32_t> tri_verts_user;  // host copy for tetmesh_tri_vertices
     std::vector<void*> allocations;
+    float lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};  // bounds of the points
+    std::mutex ws_mu;                   // the handle's workspace for ray binning
+    void* ws = nullptr;
+    int64_t ws_bytes = 0;
 };
 
 namespace {
@@ -44,6 +50,31 @@ int hip_fail(hipError_t e, const char* what) {
 void release(tm_mesh_s* m) {
     for (void* p : m->allocations) (void)hipFree(p);
     m->allocations.clear();
+    if (m->ws) (void)hipFree(m->ws);
+    m->ws = nullptr;
+    m->ws_bytes = 0;
+}
+
+// Binning configuration of a trace, or nbins = 0 when the rays are not binned.
+int sort_config(const tm_mesh_s* m, const tm_trace_opts& o, int64_t n, bool has_tmax,
+                tetrt::SortCfg* c) {
+    c->nbins = 0;
+    // automatic: bin batches of secondary-style rays (with tmax) of at least 2^18 rays
+    const bool on = o.sort == 2 || (o.sort == 0 && has_tmax && n >= (int64_t(1) << 18));
+    if (!on) return TM_OK;
+    c->cells_log2 = o.sort_cells_log2 ? o.sort_cells_log2 : 5;
+    c->dirq = o.sort_dirq ? o.sort_dirq : 4;
+    if (c->cells_log2 < 1 || c->cells_log2 > 7 || c->dirq < 1 || c->dirq > 8)
+        return fail(TM_ERR_ARG, "trace_closest: sort_cells_log2 must be in [1, 7] and sort_dirq in [1, 8]");
+    const int64_t G = int64_t(1) << c->cells_log2;
+    c->nbins = G * G * G * int64_t(c->dirq) * c->dirq * c->dirq;
+    if (c->nbins > (int64_t(1) << 24))
+        return fail(TM_ERR_ARG, "trace_closest: %lld sort bins (at most 2^24)", (long long)c->nbins);
+    for (int a = 0; a < 3; ++a) {
+        c->lo[a] = m->lo[a];
+        c->inv[a] = m->ext[a] > 0 ? float(double(G) / m->ext[a]) : 0.0f;
+    }
+    return TM_OK;
 }
 
 // Copy a host vector into a new device buffer owned by the handle.
@@ -151,6 +182,15 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     m->hot_bytes = hot;
     m->cold_bytes = cold;
     m->tri_verts_user.swap(pm.tri_verts_user);
+    for (int a = 0; a < 3; ++a) {
+        float lo = points[a], hi = points[a];
+        for (int64_t i = 1; i < n_points; ++i) {
+            lo = std::fmin(lo, points[3 * i + a]);
+            hi = std::fmax(hi, points[3 * i + a]);
+        }
+        m->lo[a] = lo;
+        m->ext[a] = hi - lo;
+    }
     *out = m;
     return TM_OK;
 }
@@ -169,7 +209,8 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
         return fail(TM_ERR_ARG, "trace_closest: NULL required array");
     if ((reinterpret_cast<uintptr_t>(d_bary) & 7) || (reinterpret_cast<uintptr_t>(d_hit_tets) & 7))
         return fail(TM_ERR_ARG, "trace_closest: bary / hit_tets must be 8-byte aligned");
-    tm_trace_opts o = {0, 0, 0, 0, 0, 0};
+    tm_trace_opts o;
+    std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
     if (o.max_steps < 0) return fail(TM_ERR_ARG, "trace_closest: negative max_steps");
     if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
@@ -178,7 +219,15 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     if (o.refill < 0 || o.refill > 64) return fail(TM_ERR_ARG, "trace_closest: refill must be in [0, 64]");
     if (o.grid_cap < 0) return fail(TM_ERR_ARG, "trace_closest: negative grid_cap");
     if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "trace_closest: xcds must be in [0, 64]");
+    if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "trace_closest: sort must be 0, 1 or 2");
+    if (!(o.eps == 0.0f)) return fail(TM_ERR_ARG, "trace_closest: eps must be 0 (no FP64 re-evaluation)");
+    if (o.workspace_bytes < 0 || (o.workspace_bytes > 0 && !o.workspace))
+        return fail(TM_ERR_ARG, "trace_closest: bad workspace");
+    tetrt::SortCfg sc;
+    int rc = sort_config(m, o, n_rays, d_tmax != nullptr, &sc);
+    if (rc != TM_OK) return rc;
     tetrt::RayArgs r;
+    r.perm = nullptr;
     r.orig = d_orig;
     r.dir = d_dir;
     r.tmax = d_tmax;
@@ -205,8 +254,62 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     const int64_t lanes = int64_t(c.cus) * 4 * 64 * c.waves_per_simd;
     (void)lanes;
     c.kernel = o.kernel ? o.kernel : 1;
-    hipError_t e = tetrt::launch_trace(m->dev, r, c, static_cast<hipStream_t>(hip_stream));
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e;
+    if (sc.nbins > 0) {
+        // bin the rays, then trace them in bin order through the permutation
+        const int64_t need = tetrt::sort_workspace_bytes(n_rays, sc.nbins);
+        void* ws = o.workspace;
+        std::unique_lock<std::mutex> lock(m->ws_mu, std::defer_lock);
+        if (ws) {
+            if (o.workspace_bytes < need)
+                return fail(TM_ERR_ARG, "trace_closest: workspace of %lld bytes, %lld needed",
+                            (long long)o.workspace_bytes, (long long)need);
+        } else {
+            lock.lock();
+            if (m->ws_bytes < need) {
+                // grow the handle's workspace once; earlier work using it must end first
+                if (m->ws) {
+                    e = hipDeviceSynchronize();
+                    if (e != hipSuccess) return hip_fail(e, "trace_closest: synchronize");
+                    (void)hipFree(m->ws);
+                    m->ws = nullptr;
+                    m->ws_bytes = 0;
+                }
+                e = hipMalloc(&m->ws, size_t(need));
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    m->ws = nullptr;
+                    return fail(TM_ERR_OOM, "trace_closest: workspace of %lld bytes: %s", (long long)need,
+                                hipGetErrorString(e));
+                }
+                m->ws_bytes = need;
+            }
+            ws = m->ws;
+        }
+        int32_t* perm = nullptr;
+        e = tetrt::launch_sort(sc, d_orig, d_dir, n_rays, ws, &perm, stream);
+        if (e != hipSuccess) return hip_fail(e, "trace_closest: ray binning launch");
+        r.perm = perm;
+    }
+    e = tetrt::launch_trace(m->dev, r, c, stream);
     if (e != hipSuccess) return hip_fail(e, "trace_closest: kernel launch");
+    return TM_OK;
+}
+
+int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_present,
+                            const tm_trace_opts* opts, int64_t* bytes) {
+    g_error.clear();
+    if (!m || !bytes) return fail(TM_ERR_ARG, "tetmesh_trace_workspace: NULL argument");
+    if (n_rays < 0 || n_rays > int64_t(0x7FFFFFFF))
+        return fail(TM_ERR_ARG, "tetmesh_trace_workspace: n_rays out of range");
+    tm_trace_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    tetrt::SortCfg sc;
+    int rc = sort_config(m, o, n_rays, d_tmax_present != nullptr, &sc);
+    if (rc != TM_OK) return rc;
+    *bytes = sc.nbins > 0 ? tetrt::sort_workspace_bytes(n_rays, sc.nbins) : 0;
     return TM_OK;
 }
 

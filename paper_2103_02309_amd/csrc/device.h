@@ -32,6 +32,7 @@ struct DevMesh {
 };
 
 struct RayArgs {
+    const int32_t* perm;       // optional: lane j of the grid traces ray perm[j]
     const float* orig;
     const float* dir;
     const float* tmax;
@@ -57,6 +58,21 @@ struct LaunchCfg {
 };
 
 hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s);
+
+// Ray binning: key = Morton index of the origin's cell in a 2^cells_log2 grid
+// over [lo, lo + G/inv), then the direction quantised to dirq levels per axis.
+struct SortCfg {
+    int32_t cells_log2;
+    int32_t dirq;
+    float lo[3];
+    float inv[3];             // cells per unit length, per axis
+    int64_t nbins;            // 2^(3 cells_log2) * dirq^3
+};
+
+int64_t sort_workspace_bytes(int64_t n, int64_t nbins);
+// Fills the permutation (inside ws) that orders the rays by bin.
+hipError_t launch_sort(const SortCfg& c, const float* orig, const float* dir, int64_t n, void* ws,
+                       int32_t** perm_out, hipStream_t s);
 hipError_t launch_locate(const DevMesh& m, int64_t n, const float* pts, int32_t* out,
                          int32_t max_steps, hipStream_t s);
 

@@ -567,8 +567,9 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t 
 template <bool TMAX, int LAYOUT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_trace(DevMesh m, RayArgs r, uint32_t xcds) {
-    const int64_t i = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds)) * blockDim.x + threadIdx.x;
-    if (i >= r.n) return;
+    const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds)) * blockDim.x + threadIdx.x;
+    if (j >= r.n) return;
+    const int64_t i = r.perm ? int64_t(r.perm[j]) : j;
     const Mem M = make_mem<LAYOUT>(m);
     Ray s;
     if (!setup_ray<TMAX, LAYOUT>(m, M, r, i, s)) return;
@@ -579,15 +580,17 @@ k_trace(DevMesh m, RayArgs r, uint32_t xcds) {
     finish_ray<TMAX>(m, M, r, i, s);
 }
 
-// Persistent lanes: lane g of the grid owns rays g, g + L, g + 2L, ... (L =
-// lanes in the grid), so neighbouring lanes start on neighbouring rays.  A
+// Persistent lanes: lane g of the grid owns the rays at positions g, g + L,
+// g + 2L, ... of the ray order (L = lanes in the grid), so neighbouring lanes
+// start on neighbouring rays.  A
 // wave walks until `refill` of its lanes have finished, then writes those
 // results and sets up their next rays together, so the dependent loads of
 // set-up and result are paid once per batch rather than on every step.
 template <bool TMAX, int LAYOUT>
 __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, int32_t refill) {
     const int64_t L = int64_t(gridDim.x) * blockDim.x;
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;   // position in the ray order
+    int64_t i = 0;                                                 // the ray at that position
     const Mem M = make_mem<LAYOUT>(m);
     Ray s;
     bool has = false;   // the lane holds ray i
@@ -597,12 +600,13 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
             finish_ray<TMAX>(m, M, r, i, s);
             done = false;
             has = false;
-            i += L;
+            j += L;
         }
         if (!has) {
-            while (i < r.n) {
+            while (j < r.n) {
+                i = r.perm ? int64_t(r.perm[j]) : j;
                 if (setup_ray<TMAX, LAYOUT>(m, M, r, i, s)) { has = true; break; }
-                i += L;
+                j += L;
             }
         }
         if (!__any(has)) break;

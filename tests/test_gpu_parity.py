@@ -225,3 +225,34 @@ def test_layouts_agree(tetrt, tiny_mesh):
     for other in outs[1:]:
         for k in outs[0]:
             assert np.array_equal(outs[0][k], other[k], equal_nan=True), k
+
+
+@pytest.mark.parametrize("kw", [dict(sort=2), dict(sort=2, sort_cells_log2=2, sort_dirq=1),
+                                dict(sort=2, sort_cells_log2=6, sort_dirq=4),
+                                dict(sort=2, kernel=2, grid_cap=3, refill=8)])
+def test_binned_rays_match_unbinned(tiny, kw):
+    """Tracing in bin order through the permutation changes no result, and the
+    results stay at the caller's positions."""
+    m, om, mesh = tiny
+    o, d = random_interior_rays(40000, 43)
+    tm = np.random.default_rng(6).uniform(0.0, 0.6, 40000).astype(np.float32)
+    a = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), want_tets=True, want_steps=True, sort=1))
+    b = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), want_tets=True, want_steps=True, **kw))
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_binning_with_caller_workspace(tiny, tetrt):
+    m, om, mesh = tiny
+    o, d = random_interior_rays(30000, 47)
+    need = mesh.workspace_bytes(30000, True, sort=2)
+    assert need >= 4 * 30000
+    assert mesh.workspace_bytes(30000, True, sort=1) == 0
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    a = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(np.full(30000, 0.3, np.float32)), sort=1))
+    b = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(np.full(30000, 0.3, np.float32)), sort=2,
+                         workspace=ws))
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    with pytest.raises(tetrt.TetRTError):
+        mesh.trace(_dev(o), _dev(d), sort=2, workspace=ws[: need // 2])
