@@ -109,12 +109,14 @@ typedef struct {
                             contiguous range of blocks each; 0 or 1 = off (round-robin
                             placement, which balances the dies) */
     int32_t sort;        /* ray binning before the walk: 0 = automatic (on for batches of at
-                            least 2^18 rays that carry tmax), 1 = off, 2 = on.  Binned rays
-                            are grouped by origin cell (Morton order of a 2^k grid over the
-                            mesh bounds), then by direction, and traced in that order; the
-                            outputs stay at the caller's positions */
-    int32_t sort_cells_log2; /* k above, 1..7 (0 = 5: 32^3 cells) */
-    int32_t sort_dirq;   /* direction bins per axis, 1..8 (0 = 4) */
+                            least 2^18 rays that carry tmax), 1 = off, 2 = on.  Inside each
+                            chunk of consecutive rays, rays are grouped by quantised
+                            direction, then by the low bits of the Morton index of their
+                            origin's cell, and traced in that order; the outputs stay at
+                            the caller's positions */
+    int32_t sort_chunk_log2; /* rays per chunk = 2^this, 10..13 (0 = 12) */
+    int32_t sort_cells_log2; /* origin cells per axis = 2^this, 1..7 (0 = 5) */
+    int32_t sort_dirq;   /* direction bins per axis, 1..4 (0 = 4) */
     float eps;           /* reserved, must be 0 */
     void* workspace;     /* device scratch for binning, or NULL: the handle then uses (and
                             grows) a workspace of its own, so binned traces on one handle

@@ -55,24 +55,22 @@ void release(tm_mesh_s* m) {
     m->ws_bytes = 0;
 }
 
-// Binning configuration of a trace, or nbins = 0 when the rays are not binned.
+// Binning configuration of a trace; *on = false when the rays are not binned.
 int sort_config(const tm_mesh_s* m, const tm_trace_opts& o, int64_t n, bool has_tmax,
-                tetrt::SortCfg* c) {
-    c->nbins = 0;
+                tetrt::SortCfg* c, bool* on) {
     // automatic: bin batches of secondary-style rays (with tmax) of at least 2^18 rays
-    const bool on = o.sort == 2 || (o.sort == 0 && has_tmax && n >= (int64_t(1) << 18));
-    if (!on) return TM_OK;
+    *on = o.sort == 2 || (o.sort == 0 && has_tmax && n >= (int64_t(1) << 18));
+    c->chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 12;
     c->cells_log2 = o.sort_cells_log2 ? o.sort_cells_log2 : 5;
     c->dirq = o.sort_dirq ? o.sort_dirq : 4;
-    if (c->cells_log2 < 1 || c->cells_log2 > 7 || c->dirq < 1 || c->dirq > 8)
-        return fail(TM_ERR_ARG, "trace_closest: sort_cells_log2 must be in [1, 7] and sort_dirq in [1, 8]");
-    const int64_t G = int64_t(1) << c->cells_log2;
-    c->nbins = G * G * G * int64_t(c->dirq) * c->dirq * c->dirq;
-    if (c->nbins > (int64_t(1) << 24))
-        return fail(TM_ERR_ARG, "trace_closest: %lld sort bins (at most 2^24)", (long long)c->nbins);
+    if (c->chunk_log2 < 10 || c->chunk_log2 > 13 || c->cells_log2 < 1 || c->cells_log2 > 7 ||
+        c->dirq < 1 || c->dirq > 4)
+        return fail(TM_ERR_ARG, "trace_closest: sort_chunk_log2 must be in [10, 13], sort_cells_log2 "
+                                "in [1, 7] and sort_dirq in [1, 4]");
+    const double G = double(int64_t(1) << c->cells_log2);
     for (int a = 0; a < 3; ++a) {
         c->lo[a] = m->lo[a];
-        c->inv[a] = m->ext[a] > 0 ? float(double(G) / m->ext[a]) : 0.0f;
+        c->inv[a] = m->ext[a] > 0 ? float(G / m->ext[a]) : 0.0f;
     }
     return TM_OK;
 }
@@ -224,7 +222,8 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     if (o.workspace_bytes < 0 || (o.workspace_bytes > 0 && !o.workspace))
         return fail(TM_ERR_ARG, "trace_closest: bad workspace");
     tetrt::SortCfg sc;
-    int rc = sort_config(m, o, n_rays, d_tmax != nullptr, &sc);
+    bool binned = false;
+    int rc = sort_config(m, o, n_rays, d_tmax != nullptr, &sc, &binned);
     if (rc != TM_OK) return rc;
     tetrt::RayArgs r;
     r.perm = nullptr;
@@ -256,9 +255,9 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     c.kernel = o.kernel ? o.kernel : 1;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     hipError_t e;
-    if (sc.nbins > 0) {
+    if (binned) {
         // bin the rays, then trace them in bin order through the permutation
-        const int64_t need = tetrt::sort_workspace_bytes(n_rays, sc.nbins);
+        const int64_t need = tetrt::sort_workspace_bytes(n_rays);
         void* ws = o.workspace;
         std::unique_lock<std::mutex> lock(m->ws_mu, std::defer_lock);
         if (ws) {
@@ -307,9 +306,10 @@ int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_prese
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
     tetrt::SortCfg sc;
-    int rc = sort_config(m, o, n_rays, d_tmax_present != nullptr, &sc);
+    bool binned = false;
+    int rc = sort_config(m, o, n_rays, d_tmax_present != nullptr, &sc, &binned);
     if (rc != TM_OK) return rc;
-    *bytes = sc.nbins > 0 ? tetrt::sort_workspace_bytes(n_rays, sc.nbins) : 0;
+    *bytes = binned ? tetrt::sort_workspace_bytes(n_rays) : 0;
     return TM_OK;
 }
 

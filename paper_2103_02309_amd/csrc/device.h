@@ -59,17 +59,18 @@ struct LaunchCfg {
 
 hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s);
 
-// Ray binning: key = Morton index of the origin's cell in a 2^cells_log2 grid
-// over [lo, lo + G/inv), then the direction quantised to dirq levels per axis.
+// Ray binning inside chunks of 2^chunk_log2 consecutive rays: by direction
+// quantised to dirq levels per axis, then by the low bits of the Morton index
+// of the origin's cell in a 2^cells_log2 grid over [lo, lo + G/inv).
 struct SortCfg {
-    int32_t cells_log2;
-    int32_t dirq;
+    int32_t chunk_log2;       // 10..13
+    int32_t cells_log2;       // 1..7
+    int32_t dirq;             // 1..4
     float lo[3];
     float inv[3];             // cells per unit length, per axis
-    int64_t nbins;            // 2^(3 cells_log2) * dirq^3
 };
 
-int64_t sort_workspace_bytes(int64_t n, int64_t nbins);
+int64_t sort_workspace_bytes(int64_t n);
 // Fills the permutation (inside ws) that orders the rays by bin.
 hipError_t launch_sort(const SortCfg& c, const float* orig, const float* dir, int64_t n, void* ws,
                        int32_t** perm_out, hipStream_t s);

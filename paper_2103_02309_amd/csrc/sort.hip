@@ -1,10 +1,13 @@
-// Ray binning for coherent traversal: rays are grouped by the cell of their
-// origin (Morton order of a 2^k grid over the mesh bounds) and then by a
-// quantised direction, with a counting sort (count, exclusive scan, scatter).
-// The walk then takes rays in this order through a permutation, so that the
-// lanes of a wavefront start close together and head the same way, and visit
-// the same tet records and points.  Order within a bin is not deterministic;
-// results are per ray and do not depend on it.
+// Ray binning for coherent traversal.  The ray order a caller produces is
+// usually already coherent in origin (pixel tiles, hit points of neighbouring
+// pixels); what breaks a wavefront's coherence is secondary rays that leave a
+// point in many directions.  So rays are regrouped inside chunks of 2^c
+// consecutive rays: by quantised direction first, then by the low bits of the
+// Morton index of their origin's cell in a grid over the mesh bounds.  Each
+// chunk is counting-sorted by one workgroup in LDS (no global atomics, one pass
+// over the rays), and the walk takes rays through the resulting permutation.
+// The order within a bin is not deterministic; results are per ray and do not
+// depend on it.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -15,7 +18,7 @@ namespace tetrt {
 
 namespace {
 
-constexpr int kScanBlock = 1024;   // bins per scan block (256 threads x 4)
+constexpr int kMinorBits = 4;   // origin-cell bits below the direction bin
 
 __device__ __forceinline__ uint32_t spread3(uint32_t x) {
     // bits of x (at most 10) to every third bit
@@ -27,135 +30,98 @@ __device__ __forceinline__ uint32_t spread3(uint32_t x) {
     return x;
 }
 
-__device__ __forceinline__ int cell_of(float v, float lo, float inv, int G) {
+__device__ __forceinline__ uint32_t cell_of(float v, float lo, float inv, int G) {
     // clamped in float first, so NaN and infinities land in a valid cell
-    const float g = fminf(fmaxf((v - lo) * inv, 0.0f), float(G - 1));
-    return int(g);
+    return uint32_t(fminf(fmaxf((v - lo) * inv, 0.0f), float(G - 1)));
 }
 
+__device__ __forceinline__ uint32_t qdir(float v, float h, int q) {
+    return uint32_t(fminf(fmaxf((v + 1.0f) * h, 0.0f), float(q - 1)));
+}
+
+// key in [0, dirq^3 * 2^kMinorBits)
 __device__ __forceinline__ uint32_t ray_key(const SortCfg& c, float ox, float oy, float oz, float dx,
                                             float dy, float dz) {
     const int G = 1 << c.cells_log2;
-    const uint32_t cx = uint32_t(cell_of(ox, c.lo[0], c.inv[0], G));
-    const uint32_t cy = uint32_t(cell_of(oy, c.lo[1], c.inv[1], G));
-    const uint32_t cz = uint32_t(cell_of(oz, c.lo[2], c.inv[2], G));
-    const uint32_t cell = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
+    const uint32_t cell = (spread3(cell_of(ox, c.lo[0], c.inv[0], G)) << 2) |
+                          (spread3(cell_of(oy, c.lo[1], c.inv[1], G)) << 1) |
+                          spread3(cell_of(oz, c.lo[2], c.inv[2], G));
     const float il = rsqrtf(fmaxf(dx * dx + dy * dy + dz * dz, 1e-30f));
     const int q = c.dirq;
     const float h = 0.5f * float(q);
-    const uint32_t bx = uint32_t(fminf(fmaxf((dx * il + 1.0f) * h, 0.0f), float(q - 1)));
-    const uint32_t by = uint32_t(fminf(fmaxf((dy * il + 1.0f) * h, 0.0f), float(q - 1)));
-    const uint32_t bz = uint32_t(fminf(fmaxf((dz * il + 1.0f) * h, 0.0f), float(q - 1)));
-    return cell * uint32_t(q * q * q) + (bx * uint32_t(q) + by) * uint32_t(q) + bz;
+    const uint32_t dirbin = (qdir(dx * il, h, q) * uint32_t(q) + qdir(dy * il, h, q)) * uint32_t(q) +
+                            qdir(dz * il, h, q);
+    return (dirbin << kMinorBits) | (cell & ((1u << kMinorBits) - 1u));
 }
 
-__global__ void k_fill_zero(uint32_t* p, int64_t n) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
-}
-
-__global__ void k_count(SortCfg c, const float* orig, const float* dir, int64_t n, uint32_t* bins) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t k = ray_key(c, orig[3 * i], orig[3 * i + 1], orig[3 * i + 2], dir[3 * i],
-                               dir[3 * i + 1], dir[3 * i + 2]);
-    atomicAdd(&bins[k], 1u);
-}
-
-// Exclusive scan of kScanBlock bins per block, in place; the block's total goes
-// to sums[blockIdx.x].
-__global__ void __launch_bounds__(256) k_scan_block(uint32_t* bins, int64_t nbins, uint32_t* sums) {
+template <int CHUNK_LOG2>
+__global__ void __launch_bounds__(256) k_chunk_sort(SortCfg c, const float* orig, const float* dir,
+                                                    int64_t n, int32_t* perm) {
+    constexpr int C = 1 << CHUNK_LOG2;
+    constexpr int K = 64 << kMinorBits;            // dirq <= 4
+    __shared__ uint32_t hist[K];
+    __shared__ uint16_t keys[C];
+    const int64_t base = int64_t(blockIdx.x) * C;
+    const int cnt = int(min<int64_t>(C, n - base));
+    const int nb = c.dirq * c.dirq * c.dirq << kMinorBits;
+    for (int k = threadIdx.x; k < K; k += 256) hist[k] = 0u;
+    __syncthreads();
+    for (int r = threadIdx.x; r < cnt; r += 256) {
+        const int64_t i = base + r;
+        const uint32_t key = ray_key(c, orig[3 * i], orig[3 * i + 1], orig[3 * i + 2], dir[3 * i],
+                                     dir[3 * i + 1], dir[3 * i + 2]);
+        keys[r] = uint16_t(key);
+        atomicAdd(&hist[key], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the nb counters: 256 threads x (K / 256) each
     __shared__ uint32_t part[256];
-    const int64_t base = int64_t(blockIdx.x) * kScanBlock + threadIdx.x * 4;
-    uint32_t v[4];
+    constexpr int per = K / 256;
+    uint32_t v[per];
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        v[k] = base + k < nbins ? bins[base + k] : 0u;
+    for (int k = 0; k < per; ++k) {
+        const int b = threadIdx.x * per + k;
+        v[k] = b < nb ? hist[b] : 0u;
         acc += v[k];
     }
     part[threadIdx.x] = acc;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {   // inclusive scan of the thread totals
-        const uint32_t add = threadIdx.x >= unsigned(off) ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += add;
-        __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - acc;     // exclusive prefix of this thread
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (base + k < nbins) bins[base + k] = run;
-        run += v[k];
-    }
-    if (threadIdx.x == 255) sums[blockIdx.x] = part[255];
-}
-
-// Exclusive scan of the block totals in one block of 1024 threads.
-__global__ void __launch_bounds__(1024) k_scan_sums(uint32_t* sums, int32_t nsums) {
-    __shared__ uint32_t part[1024];
-    const int per = (nsums + 1023) / 1024;
-    const int b = threadIdx.x * per;
-    uint32_t acc = 0;
-    for (int k = 0; k < per; ++k)
-        if (b + k < nsums) acc += sums[b + k];
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
+    for (int off = 1; off < 256; off <<= 1) {
         const uint32_t add = threadIdx.x >= unsigned(off) ? part[threadIdx.x - off] : 0u;
         __syncthreads();
         part[threadIdx.x] += add;
         __syncthreads();
     }
     uint32_t run = part[threadIdx.x] - acc;
-    for (int k = 0; k < per; ++k)
-        if (b + k < nsums) {
-            const uint32_t x = sums[b + k];
-            sums[b + k] = run;
-            run += x;
-        }
-}
-
-__global__ void k_scan_add(uint32_t* bins, int64_t nbins, const uint32_t* sums) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < nbins) bins[i] += sums[i / kScanBlock];
-}
-
-__global__ void k_scatter(SortCfg c, const float* orig, const float* dir, int64_t n, uint32_t* bins,
-                          int32_t* perm) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t k = ray_key(c, orig[3 * i], orig[3 * i + 1], orig[3 * i + 2], dir[3 * i],
-                               dir[3 * i + 1], dir[3 * i + 2]);
-    const uint32_t pos = atomicAdd(&bins[k], 1u);
-    perm[pos] = int32_t(i);
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        const int b = threadIdx.x * per + k;
+        if (b < nb) hist[b] = run;
+        run += v[k];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < cnt; r += 256) {
+        const uint32_t pos = atomicAdd(&hist[keys[r]], 1u);
+        perm[base + pos] = int32_t(base + r);
+    }
 }
 
 }  // namespace
 
-int64_t sort_workspace_bytes(int64_t n, int64_t nbins) {
-    const int64_t nsums = (nbins + kScanBlock - 1) / kScanBlock;
-    auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
-    return up(4 * nbins) + up(4 * nsums) + up(4 * n);
-}
+int64_t sort_workspace_bytes(int64_t n) { return (4 * n + 255) / 256 * 256; }
 
 hipError_t launch_sort(const SortCfg& c, const float* orig, const float* dir, int64_t n, void* ws,
                        int32_t** perm_out, hipStream_t s) {
-    const int64_t nbins = c.nbins;
-    const int64_t nsums = (nbins + kScanBlock - 1) / kScanBlock;
-    auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
-    char* p = static_cast<char*>(ws);
-    uint32_t* bins = reinterpret_cast<uint32_t*>(p);
-    uint32_t* sums = reinterpret_cast<uint32_t*>(p + up(4 * nbins));
-    int32_t* perm = reinterpret_cast<int32_t*>(p + up(4 * nbins) + up(4 * nsums));
-    const int B = 256;
-    hipLaunchKernelGGL(k_fill_zero, dim3(unsigned((nbins + B - 1) / B)), dim3(B), 0, s, bins, nbins);
-    hipLaunchKernelGGL(k_count, dim3(unsigned((n + B - 1) / B)), dim3(B), 0, s, c, orig, dir, n, bins);
-    hipLaunchKernelGGL(k_scan_block, dim3(unsigned(nsums)), dim3(256), 0, s, bins, nbins, sums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, sums, int32_t(nsums));
-    hipLaunchKernelGGL(k_scan_add, dim3(unsigned((nbins + B - 1) / B)), dim3(B), 0, s, bins, nbins, sums);
-    hipLaunchKernelGGL(k_scatter, dim3(unsigned((n + B - 1) / B)), dim3(B), 0, s, c, orig, dir, n, bins,
-                       perm);
+    int32_t* perm = static_cast<int32_t*>(ws);
+    const int64_t C = int64_t(1) << c.chunk_log2;
+    const unsigned grid = unsigned((n + C - 1) / C);
+    switch (c.chunk_log2) {
+        case 10: hipLaunchKernelGGL(k_chunk_sort<10>, dim3(grid), dim3(256), 0, s, c, orig, dir, n, perm); break;
+        case 11: hipLaunchKernelGGL(k_chunk_sort<11>, dim3(grid), dim3(256), 0, s, c, orig, dir, n, perm); break;
+        case 12: hipLaunchKernelGGL(k_chunk_sort<12>, dim3(grid), dim3(256), 0, s, c, orig, dir, n, perm); break;
+        default: hipLaunchKernelGGL(k_chunk_sort<13>, dim3(grid), dim3(256), 0, s, c, orig, dir, n, perm); break;
+    }
     *perm_out = perm;
     return hipGetLastError();
 }

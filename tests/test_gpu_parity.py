@@ -228,14 +228,15 @@ def test_layouts_agree(tetrt, tiny_mesh):
 
 
 @pytest.mark.parametrize("kw", [dict(sort=2), dict(sort=2, sort_cells_log2=2, sort_dirq=1),
-                                dict(sort=2, sort_cells_log2=6, sort_dirq=4),
+                                dict(sort=2, sort_chunk_log2=10, sort_cells_log2=7, sort_dirq=3),
+                                dict(sort=2, sort_chunk_log2=13),
                                 dict(sort=2, kernel=2, grid_cap=3, refill=8)])
 def test_binned_rays_match_unbinned(tiny, kw):
     """Tracing in bin order through the permutation changes no result, and the
     results stay at the caller's positions."""
     m, om, mesh = tiny
-    o, d = random_interior_rays(40000, 43)
-    tm = np.random.default_rng(6).uniform(0.0, 0.6, 40000).astype(np.float32)
+    o, d = random_interior_rays(40001, 43)            # a ragged last chunk
+    tm = np.random.default_rng(6).uniform(0.0, 0.6, 40001).astype(np.float32)
     a = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), want_tets=True, want_steps=True, sort=1))
     b = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), want_tets=True, want_steps=True, **kw))
     for k in a:
