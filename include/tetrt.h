@@ -117,12 +117,18 @@ typedef struct {
     int32_t sort_chunk_log2; /* rays per chunk = 2^this, 10..13 (0 = 12) */
     int32_t sort_cells_log2; /* origin cells per axis = 2^this, 1..7 (0 = 5) */
     int32_t sort_dirq;   /* direction bins per axis, 1..4 (0 = 4) */
-    float eps;           /* reserved, must be 0 */
+    float eps;           /* precision variant, 0 = off.  When > 0 (one lane per ray only), a
+                            walk step whose float32 exit-face determinants det(q3, q_i) are
+                            within eps * (|q3|_1 + |q_i|_1) of zero recomputes the projections
+                            and determinants in float64 from the float32 points, basis and
+                            origin; the start tet's exit face is then also found in float64.
+                            With the scene extent 1, eps >= 1e-6 covers float32 rounding */
     void* workspace;     /* device scratch for binning, or NULL: the handle then uses (and
                             grows) a workspace of its own, so binned traces on one handle
                             must not overlap in time unless each passes its own */
     int64_t workspace_bytes; /* size of workspace (tetmesh_trace_workspace gives the need) */
-    int32_t* fp64_steps; /* reserved, must be NULL */
+    int32_t* fp64_steps; /* device int32 [n_rays] or NULL: out: walk steps decided in float64
+                            (0 when eps = 0) */
 } tm_trace_opts;
 
 /*

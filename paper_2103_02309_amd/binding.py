@@ -40,10 +40,13 @@ _TRACE_KEYS = ("max_steps", "block", "kernel", "refill", "grid_cap", "xcds", "so
                "sort_chunk_log2", "sort_cells_log2", "sort_dirq")
 
 
-def _trace_opts(kw, workspace=None):
+def _trace_opts(kw, workspace=None, fp64_steps=None, n=0):
     o = _TraceOpts()
     for k in _TRACE_KEYS:
         setattr(o, k, int(kw.pop(k, 0)))
+    o.eps = float(kw.pop("eps", 0.0))
+    if fp64_steps is not None:
+        o.fp64_steps = _dev(fp64_steps, torch.int32, n, (), "fp64_steps")
     if kw:
         raise TypeError("unknown trace options: %s" % ", ".join(sorted(kw)))
     if workspace is not None:
@@ -157,11 +160,11 @@ def tetmesh_upload(points, tets, nbrs, cflag, layout="tet20", sfc="hilbert", val
 
 
 def trace_closest(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, start_face=None,
-                  hit_tets=None, steps=None, workspace=None, stream=None, **opts):
+                  hit_tets=None, steps=None, workspace=None, fp64_steps=None, stream=None, **opts):
     """Enqueue a trace of ``orig``/``dirs`` ([n, 3] float32, device) writing into the
     given device tensors; asynchronous on ``stream`` (default: the current one).
     ``opts``: the tm_trace_opts fields (max_steps, block, kernel, refill, grid_cap,
-    xcds, sort, sort_chunk_log2, sort_cells_log2, sort_dirq)."""
+    xcds, sort, sort_chunk_log2, sort_cells_log2, sort_dirq, eps)."""
     n = int(orig.shape[0]) if orig.dim() >= 1 else 0
     args = [_dev(orig, torch.float32, n, (3,), "orig"), _dev(dirs, torch.float32, n, (3,), "dirs"),
             _dev(tmax, torch.float32, n, (), "tmax", True),
@@ -171,7 +174,7 @@ def trace_closest(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, s
             _dev(bary, torch.float32, n, (2,), "bary"),
             _dev(hit_tets, torch.int32, n, (2,), "hit_tets", True),
             _dev(steps, torch.int32, n, (), "steps", True)]
-    o = _trace_opts(dict(opts), workspace)
+    o = _trace_opts(dict(opts), workspace, fp64_steps, n)
     _check(_load().trace_closest(C.c_void_p(handle), n, *args, C.byref(o), _stream(stream)))
 
 
@@ -236,7 +239,7 @@ class Mesh:
             tetmesh_free(h)
 
     def trace(self, orig, dirs, tmax=None, start_tet=None, start_face=None, want_tets=False,
-              want_steps=False, workspace=None, stream=None, **opts):
+              want_steps=False, want_fp64=False, workspace=None, stream=None, **opts):
         n = int(orig.shape[0])
         dev = orig.device
         out = {"tri": torch.empty(n, dtype=torch.int32, device=dev),
@@ -246,6 +249,8 @@ class Mesh:
             out["hit_tets"] = torch.empty((n, 2), dtype=torch.int32, device=dev)
         if want_steps:
             out["steps"] = torch.empty(n, dtype=torch.int32, device=dev)
+        if want_fp64:
+            out["fp64_steps"] = torch.empty(n, dtype=torch.int32, device=dev)
         self.trace_into(out, orig, dirs, tmax, start_tet, start_face, workspace, stream, **opts)
         return out
 
@@ -253,7 +258,8 @@ class Mesh:
                    workspace=None, stream=None, **opts):
         trace_closest(self.handle, orig, dirs, out["tri"], out["t"], out["bary"], tmax=tmax,
                       start_tet=start_tet, start_face=start_face, hit_tets=out.get("hit_tets"),
-                      steps=out.get("steps"), workspace=workspace, stream=stream, **opts)
+                      steps=out.get("steps"), workspace=workspace,
+                      fp64_steps=out.get("fp64_steps"), stream=stream, **opts)
         return out
 
     def workspace_bytes(self, n_rays, has_tmax, **opts):

@@ -218,7 +218,10 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     if (o.grid_cap < 0) return fail(TM_ERR_ARG, "trace_closest: negative grid_cap");
     if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "trace_closest: xcds must be in [0, 64]");
     if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "trace_closest: sort must be 0, 1 or 2");
-    if (!(o.eps == 0.0f)) return fail(TM_ERR_ARG, "trace_closest: eps must be 0 (no FP64 re-evaluation)");
+    if (!(o.eps >= 0.0f) || !(o.eps < 1.0f))
+        return fail(TM_ERR_ARG, "trace_closest: eps must be in [0, 1)");
+    if (o.eps > 0.0f && o.kernel == 2)
+        return fail(TM_ERR_ARG, "trace_closest: the precision variant (eps > 0) runs one lane per ray");
     if (o.workspace_bytes < 0 || (o.workspace_bytes > 0 && !o.workspace))
         return fail(TM_ERR_ARG, "trace_closest: bad workspace");
     tetrt::SortCfg sc;
@@ -237,6 +240,7 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     r.bary = d_bary;
     r.hit_tets = d_hit_tets;
     r.steps = d_steps;
+    r.fp64_steps = o.fp64_steps;
     r.n = n_rays;
     r.max_steps = o.max_steps > 0 ? o.max_steps : 65536;
     tetrt::LaunchCfg c;
@@ -253,6 +257,7 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     const int64_t lanes = int64_t(c.cus) * 4 * 64 * c.waves_per_simd;
     (void)lanes;
     c.kernel = o.kernel ? o.kernel : 1;
+    c.eps = o.eps;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     hipError_t e;
     if (binned) {

@@ -43,6 +43,7 @@ struct RayArgs {
     float* bary;
     int32_t* hit_tets;
     int32_t* steps;
+    int32_t* fp64_steps;       // optional: walk steps decided in float64, per ray
     int64_t n;
     int32_t max_steps;
 };
@@ -55,6 +56,7 @@ struct LaunchCfg {
     int32_t cus;            // compute units of the device
     int32_t grid_cap;       // persistent: at most this many blocks (0 = no cap)
     int32_t xcds;           // one lane per ray: XCDs to give contiguous block ranges (1 = off)
+    float eps;              // > 0: precision variant (one lane per ray)
 };
 
 hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s);

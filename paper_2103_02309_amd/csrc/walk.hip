@@ -20,6 +20,12 @@
 //   stop      at a neighbour field with the top bit set: a constrained face
 //             (hit) or the boundary (miss).  The hit's t and barycentric
 //             weights are evaluated once, in float64.
+//   precision (optional, eps > 0) when one of Algorithm 1's determinants is
+//             within eps (|q3|_1 + |q_i|_1) of zero -- the only case in which
+//             float32 rounding of the projections can flip its sign -- the step
+//             recomputes the four projections and determinants in float64 from
+//             the float32 points, basis and origin and decides with those; the
+//             start tet's exit face is then also found in float64.
 //
 // Memory (paper, Sec. "Tetrahedral Mesh Representation"):
 //   Tet20  20 packed bytes {VX, N0, N1, N2, N3}, read as one 16-byte and one
@@ -43,6 +49,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "device.h"
 #include "tetrt.h"
@@ -225,6 +232,40 @@ __device__ __forceinline__ int exit_slot(float q0x, float q0y, float q1x, float 
     return d0 < 0.0f ? (d2 >= 0.0f ? 1 : 0) : (d1 < 0.0f ? 2 : 0);
 }
 
+// Precision variant: threshold, the origin of the frame, and a count of the
+// steps decided in float64.
+struct Prec {
+    float eps;
+    float ox, oy, oz;
+    int32_t n64;
+};
+
+__device__ __forceinline__ double det2d(double ax, double ay, double bx, double by) {
+    return __dmul_rn(ax, by) - __dmul_rn(ay, bx);
+}
+
+__device__ __forceinline__ void project64(const Frame& f, double pox, double poy, float4 p, double& qx,
+                                          double& qy) {
+    qx = fma(double(f.ux), double(p.x), fma(double(f.uy), double(p.y), fma(double(f.uz), double(p.z), -pox)));
+    qy = fma(double(f.vx), double(p.x), fma(double(f.vy), double(p.y), fma(double(f.vz), double(p.z), -poy)));
+}
+
+// Algorithm 1 on the float64 projections of the kept vertices a0..a2 and P.
+__device__ int exit_slot64(const Mem& M, const Frame& f, const Prec& pc, int32_t a0, int32_t a1,
+                           int32_t a2, float4 P) {
+    const double pox = fma(double(f.ux), double(pc.ox), fma(double(f.uy), double(pc.oy), double(f.uz) * double(pc.oz)));
+    const double poy = fma(double(f.vx), double(pc.ox), fma(double(f.vy), double(pc.oy), double(f.vz) * double(pc.oz)));
+    double x0, y0, x1, y1, x2, y2, x3, y3;
+    project64(f, pox, poy, load_pt(M, uint32_t(a0)), x0, y0);
+    project64(f, pox, poy, load_pt(M, uint32_t(a1)), x1, y1);
+    project64(f, pox, poy, load_pt(M, uint32_t(a2)), x2, y2);
+    project64(f, pox, poy, P, x3, y3);
+    const double d0 = det2d(x3, y3, x0, y0);
+    const double d1 = det2d(x3, y3, x1, y1);
+    const double d2 = det2d(x3, y3, x2, y2);
+    return d0 < 0.0 ? (d2 >= 0.0 ? 1 : 0) : (d1 < 0.0 ? 2 : 0);
+}
+
 // The kept face (ids a, 2-D points q, depths e) in counter-clockwise order
 // around the ray, the neighbour field across it, and `cur`: the field that the
 // next tet's record holds for this face -- the id of the tet the face belongs
@@ -249,16 +290,29 @@ __device__ __forceinline__ void make_ccw(Walk& w) {
     w.e1 = sw ? e2 : e1; w.e2 = sw ? e1 : e2;
 }
 
-// One step of the walk (Algorithm 1 with Algorithms 4-5 or 6-7), branch-free.
-template <bool DEPTH, int LAYOUT>
-__device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const Depth& g, Walk& w) {
+// One step of the walk (Algorithm 1 with Algorithms 4-5 or 6-7), branch-free
+// (apart from the rare float64 re-evaluation of the precision variant).
+template <bool DEPTH, int LAYOUT, bool PREC>
+__device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const Depth& g, Walk& w,
+                                          Prec& pc) {
     const uint32_t tet = w.next;
     const Rec R = load_rec<LAYOUT>(M, tet);
     const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ (LAYOUT == kTet32N ? w.vxn : R.vx);
     const float4 P = load_pt(M, uint32_t(id3));
     float q3x, q3y;
     project(f, P, q3x, q3y);
-    const int e = exit_slot(w.q0x, w.q0y, w.q1x, w.q1y, w.q2x, w.q2y, q3x, q3y);
+    int e = exit_slot(w.q0x, w.q0y, w.q1x, w.q1y, w.q2x, w.q2y, q3x, q3y);
+    if (PREC) {
+        const float s3 = fabsf(q3x) + fabsf(q3y);
+        const bool unsure =
+            fabsf(det2(q3x, q3y, w.q0x, w.q0y)) <= pc.eps * (s3 + fabsf(w.q0x) + fabsf(w.q0y)) ||
+            fabsf(det2(q3x, q3y, w.q1x, w.q1y)) <= pc.eps * (s3 + fabsf(w.q1x) + fabsf(w.q1y)) ||
+            fabsf(det2(q3x, q3y, w.q2x, w.q2y)) <= pc.eps * (s3 + fabsf(w.q2x) + fabsf(w.q2y));
+        if (unsure) {
+            e = exit_slot64(M, f, pc, w.a0, w.a1, w.a2, P);
+            ++pc.n64;
+        }
+    }
     const bool s0 = e == 0, s1 = e == 1;
     const int32_t x = s0 ? w.a0 : (s1 ? w.a1 : w.a2);
     const int r = (w.a0 < x) + (w.a1 < x) + (w.a2 < x) + (id3 < x);
@@ -282,36 +336,37 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
 // whose outward normal has n.D > 0 with the smallest crossing parameter s.
 // Fills the walk state (face ids, 2-D points in frame f, depths in g, the
 // neighbour field) and returns s (+inf when no face is front-facing).
-template <bool DEPTH, int LAYOUT>
+// The plane tests run in T: float, or double in the precision variant.
+template <bool DEPTH, int LAYOUT, typename T>
 __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const int32_t v[4],
                               float Xx, float Xy, float Xz, float Dx, float Dy, float Dz,
                               const Frame& f, const Depth& g, Walk& w) {
     float4 P[4];
-    float rx[4], ry[4], rz[4];
+    T rx[4], ry[4], rz[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         P[k] = load_pt(M, uint32_t(v[k]));
-        rx[k] = P[k].x - Xx;
-        ry[k] = P[k].y - Xy;
-        rz[k] = P[k].z - Xz;
+        rx[k] = T(P[k].x) - T(Xx);
+        ry[k] = T(P[k].y) - T(Xy);
+        rz[k] = T(P[k].z) - T(Xz);
     }
-    float best = INFINITY;
+    T best = T(INFINITY);
     int bj = -1;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int A = j == 0 ? 1 : 0;
         const int B = j <= 1 ? 2 : 1;
         const int C = j <= 2 ? 3 : 2;
-        const float e1x = rx[B] - rx[A], e1y = ry[B] - ry[A], e1z = rz[B] - rz[A];
-        const float e2x = rx[C] - rx[A], e2y = ry[C] - ry[A], e2z = rz[C] - rz[A];
-        float nx = e1y * e2z - e1z * e2y;
-        float ny = e1z * e2x - e1x * e2z;
-        float nz = e1x * e2y - e1y * e2x;
-        const float side = nx * (rx[j] - rx[A]) + ny * (ry[j] - ry[A]) + nz * (rz[j] - rz[A]);
-        if (side > 0.0f) { nx = -nx; ny = -ny; nz = -nz; }
-        const float nd = nx * Dx + ny * Dy + nz * Dz;
-        if (nd > 0.0f) {
-            const float s = (nx * rx[A] + ny * ry[A] + nz * rz[A]) / nd;
+        const T e1x = rx[B] - rx[A], e1y = ry[B] - ry[A], e1z = rz[B] - rz[A];
+        const T e2x = rx[C] - rx[A], e2y = ry[C] - ry[A], e2z = rz[C] - rz[A];
+        T nx = e1y * e2z - e1z * e2y;
+        T ny = e1z * e2x - e1x * e2z;
+        T nz = e1x * e2y - e1y * e2x;
+        const T side = nx * (rx[j] - rx[A]) + ny * (ry[j] - ry[A]) + nz * (rz[j] - rz[A]);
+        if (side > T(0)) { nx = -nx; ny = -ny; nz = -nz; }
+        const T nd = nx * T(Dx) + ny * T(Dy) + nz * T(Dz);
+        if (nd > T(0)) {
+            const T s = (nx * rx[A] + ny * ry[A] + nz * rz[A]) / nd;
             if (s < best) { best = s; bj = j; }
         }
     }
@@ -339,7 +394,7 @@ __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const
     if (LAYOUT == kTet32N) w.vxn = int32_t(pick4(R.w0, R.w1, R.w2, R.w3, r));
     w.cur = tet;
     make_ccw(w);
-    return best;
+    return float(best);
 }
 
 // Point location (paper, Sec. "Locating points in a tetrahedral mesh"): the
@@ -348,9 +403,9 @@ __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const
 // (parameter 1).  Constrained faces are crossed (location ignores geometry).
 // Returns the internal tet (its four ids in v) or TM_RAY_INVALID (outside) /
 // TM_RAY_STEP_CAP.
-template <int LAYOUT>
+template <int LAYOUT, bool PREC>
 __device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float py, float pz,
-                                int32_t max_steps, int32_t v[4]) {
+                                int32_t max_steps, float eps, int32_t v[4]) {
     int cx = int(floorf((px - m.lo[0]) * m.inv_cell[0]));
     int cy = int(floorf((py - m.lo[1]) * m.inv_cell[1]));
     int cz = int(floorf((pz - m.lo[2]) * m.inv_cell[2]));
@@ -375,7 +430,9 @@ __device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float 
     Depth g;
     set_depth(g, Dx, Dy, Dz, Sx, Sy, Sz);
     Walk w;
-    const float s0 = start_in_tet<true, LAYOUT>(m, M, seed, v, Sx, Sy, Sz, Dx, Dy, Dz, f, g, w);
+    using T = typename std::conditional<PREC, double, float>::type;
+    const float s0 = start_in_tet<true, LAYOUT, T>(m, M, seed, v, Sx, Sy, Sz, Dx, Dy, Dz, f, g, w);
+    Prec pc{eps, Sx, Sy, Sz, 0};
     if (!(s0 < 1.0f)) return seed;
     for (int32_t step = 0; step < max_steps; ++step) {
         const uint32_t field = w.next;
@@ -396,7 +453,7 @@ __device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float 
         if (uint32_t(tet) >= uint32_t(m.nt)) return TM_RAY_STEP_CAP;
         w.next = uint32_t(tet);
         const int32_t a0 = w.a0, a1 = w.a1, a2 = w.a2;
-        walk_step<true, LAYOUT>(M, f, g, w);
+        walk_step<true, LAYOUT, PREC>(M, f, g, w, pc);
         w.cur = tet;
         // the vertex the new face dropped: the tet is {a0, a1, a2, id3}
         const int32_t x = (w.a0 != a0) ? a0 : ((w.a1 != a1) ? a1 : a2);
@@ -422,25 +479,32 @@ struct Ray {
     int32_t steps;
 };
 
+struct Knobs {
+    float eps;                // precision variant threshold (PREC kernels)
+};
+
 __device__ __forceinline__ void write_result(const RayArgs& r, int64_t i, int32_t code, float t,
                                              float b1, float b2, int32_t front, int32_t back,
-                                             int32_t steps) {
+                                             int32_t steps, int32_t n64 = 0) {
     r.tri[i] = code;
     r.t[i] = t;
     reinterpret_cast<float2*>(r.bary)[i] = make_float2(b1, b2);
     if (r.hit_tets) reinterpret_cast<int2*>(r.hit_tets)[i] = make_int2(front, back);
     if (r.steps) r.steps[i] = steps;
+    if (r.fp64_steps) r.fp64_steps[i] = n64;
 }
 
-__device__ __forceinline__ void write_code(const RayArgs& r, int64_t i, int32_t code, int32_t steps) {
+__device__ __forceinline__ void write_code(const RayArgs& r, int64_t i, int32_t code, int32_t steps,
+                                           int32_t n64 = 0) {
     const float NaN = __int_as_float(0x7fc00000);
-    write_result(r, i, code, NaN, NaN, NaN, -1, -1, steps);
+    write_result(r, i, code, NaN, NaN, NaN, -1, -1, steps, n64);
 }
 
 // Set-up of ray i.  Returns true when the ray needs walking (state in s);
 // false when its result is already written.
-template <bool TMAX, int LAYOUT>
-__device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, Ray& s) {
+template <bool TMAX, int LAYOUT, bool PREC>
+__device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, Ray& s,
+                          float eps) {
     const float ox = r.orig[3 * i], oy = r.orig[3 * i + 1], oz = r.orig[3 * i + 2];
     const float dx = r.dir[3 * i], dy = r.dir[3 * i + 1], dz = r.dir[3 * i + 2];
     s.tmax = TMAX ? r.tmax[i] : INFINITY;
@@ -488,13 +552,14 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
         const int4 sv = reinterpret_cast<const int4*>(m.tetv)[tet];
         v[0] = sv.x; v[1] = sv.y; v[2] = sv.z; v[3] = sv.w;
     } else {
-        tet = locate_point<LAYOUT>(m, M, ox, oy, oz, r.max_steps, v);
+        tet = locate_point<LAYOUT, PREC>(m, M, ox, oy, oz, r.max_steps, eps, v);
         if (tet < 0) { write_code(r, i, tet, 0); return false; }
     }
     specialized_basis(dx, dy, dz, s.f);
     set_origin(s.f, ox, oy, oz);
     if (TMAX) set_depth(s.g, dx, dy, dz, ox, oy, oz);
-    const float sx = start_in_tet<TMAX, LAYOUT>(m, M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w);
+    using T = typename std::conditional<PREC, double, float>::type;
+    const float sx = start_in_tet<TMAX, LAYOUT, T>(m, M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w);
     if (!(sx < INFINITY)) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
     return true;
 }
@@ -512,17 +577,18 @@ __device__ __forceinline__ bool walk_on(const Ray& s, int32_t max_steps) {
 // the Moller-Trumbore form in float64 with the triangle's vertices in ascending
 // caller-id order, so the weights are those of its 2nd and 3rd vertex.
 template <bool TMAX>
-__device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, const Ray& s) {
+__device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, const Ray& s,
+                           int32_t n64 = 0) {
     const uint32_t nx = s.w.next;
     if (!(nx & 0x80000000u)) {
         // tmax early-out, else the step cap
         const bool beyond = TMAX && (fminf(s.w.e0, fminf(s.w.e1, s.w.e2)) > s.tmax);
-        write_code(r, i, beyond ? TM_RAY_MISS : TM_RAY_STEP_CAP, s.steps);
+        write_code(r, i, beyond ? TM_RAY_MISS : TM_RAY_STEP_CAP, s.steps, n64);
         return;
     }
-    if (nx == kBoundary) { write_code(r, i, TM_RAY_MISS, s.steps); return; }
+    if (nx == kBoundary) { write_code(r, i, TM_RAY_MISS, s.steps, n64); return; }
     const uint32_t cf = nx & kIdMask;
-    if (cf >= uint32_t(m.ntri)) { write_code(r, i, TM_RAY_STEP_CAP, s.steps); return; }
+    if (cf >= uint32_t(m.ntri)) { write_code(r, i, TM_RAY_STEP_CAP, s.steps, n64); return; }
     // reload the ray from memory rather than keeping it in registers through the walk
     asm volatile("" ::: "memory");
     const int4 fv = reinterpret_cast<const int4*>(m.cfv)[cf];
@@ -540,7 +606,7 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
     const double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
     const double bv = (Dx * qx + Dy * qy + Dz * qz) * inv;
     const double th = (e2x * qx + e2y * qy + e2z * qz) * inv;
-    if (TMAX && th > double(s.tmax)) { write_code(r, i, TM_RAY_MISS, s.steps); return; }
+    if (TMAX && th > double(s.tmax)) { write_code(r, i, TM_RAY_MISS, s.steps, n64); return; }
     int32_t front = -1, back = -1;
     if (r.hit_tets) {
         const int4 ft = reinterpret_cast<const int4*>(m.cft)[cf];
@@ -548,12 +614,13 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
         front = m.t_new2old[s.w.cur];
         back = other >= 0 ? m.t_new2old[other] : -1;
     }
-    write_result(r, i, int32_t(cf), float(th), float(bu), float(bv), front, back, s.steps);
+    write_result(r, i, int32_t(cf), float(th), float(bu), float(bv), front, back, s.steps, n64);
 }
 
 // One lane per ray: set-up, walk, result.
 // 8 waves per SIMD (at most 64 VGPRs): the walk is latency-bound, so occupancy
-// is what hides the memory round trips.
+// is what hides the memory round trips.  The precision variant carries float64
+// code and settles for 4 waves rather than spilling.
 // The dispatcher deals blocks to the XCDs round-robin (block b runs on XCD
 // b mod X).  Renumbering so that each XCD gets one contiguous run of blocks
 // keeps neighbouring rays -- which visit the same tets -- on one L2.
@@ -564,20 +631,26 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t 
     return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
 }
 
-template <bool TMAX, int LAYOUT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
-k_trace(DevMesh m, RayArgs r, uint32_t xcds) {
+template <bool TMAX, int LAYOUT, bool PREC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 4 : 8)))
+k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds)) * blockDim.x + threadIdx.x;
     if (j >= r.n) return;
     const int64_t i = r.perm ? int64_t(r.perm[j]) : j;
     const Mem M = make_mem<LAYOUT>(m);
     Ray s;
-    if (!setup_ray<TMAX, LAYOUT>(m, M, r, i, s)) return;
+    if (!setup_ray<TMAX, LAYOUT, PREC>(m, M, r, i, s, kn.eps)) return;
+    Prec pc{kn.eps, 0.0f, 0.0f, 0.0f, 0};
+    if (PREC) {
+        pc.ox = r.orig[3 * i];
+        pc.oy = r.orig[3 * i + 1];
+        pc.oz = r.orig[3 * i + 2];
+    }
     while (walk_on<TMAX>(s, r.max_steps)) {
-        walk_step<TMAX, LAYOUT>(M, s.f, s.g, s.w);
+        walk_step<TMAX, LAYOUT, PREC>(M, s.f, s.g, s.w, pc);
         ++s.steps;
     }
-    finish_ray<TMAX>(m, M, r, i, s);
+    finish_ray<TMAX>(m, M, r, i, s, pc.n64);
 }
 
 // Persistent lanes: lane g of the grid owns the rays at positions g, g + L,
@@ -605,7 +678,7 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
         if (!has) {
             while (j < r.n) {
                 i = r.perm ? int64_t(r.perm[j]) : j;
-                if (setup_ray<TMAX, LAYOUT>(m, M, r, i, s)) { has = true; break; }
+                if (setup_ray<TMAX, LAYOUT, false>(m, M, r, i, s, 0.0f)) { has = true; break; }
                 j += L;
             }
         }
@@ -615,7 +688,8 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
             done = has && !go;
             if (__popcll(__ballot(done)) >= uint32_t(refill) || !__any(go)) break;
             if (go) {
-                walk_step<TMAX, LAYOUT>(M, s.f, s.g, s.w);
+                Prec pc{0.0f, 0.0f, 0.0f, 0.0f, 0};
+                walk_step<TMAX, LAYOUT, false>(M, s.f, s.g, s.w, pc);
                 ++s.steps;
             }
         }
@@ -625,13 +699,15 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
 template <int LAYOUT>
 __global__ void __launch_bounds__(256) k_locate(DevMesh m, int64_t n, const float* pts, int32_t* out,
                                                 int32_t max_steps) {
+    // location is always decided with the float64 re-evaluation of near-zero
+    // determinants: it is short, and a wrong tet there would start every ray wrong
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const Mem M = make_mem<LAYOUT>(m);
     const float px = pts[3 * i], py = pts[3 * i + 1], pz = pts[3 * i + 2];
     if (!isfinite(px + py + pz)) { out[i] = -1; return; }
     int32_t v[4];
-    const int32_t t = locate_point<LAYOUT>(m, M, px, py, pz, max_steps, v);
+    const int32_t t = locate_point<LAYOUT, true>(m, M, px, py, pz, max_steps, 1e-6f, v);
     out[i] = t >= 0 ? m.t_new2old[t] : (t == TM_RAY_STEP_CAP ? -2 : -1);
 }
 
@@ -647,9 +723,12 @@ void launch_trace_t(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipS
         const int32_t refill = std::min(64, std::max(1, c.refill));
         hipLaunchKernelGGL((k_trace_persistent<TMAX, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s,
                            m, r, refill);
+    } else if (c.eps > 0.0f) {
+        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, true>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m,
+                           r, uint32_t(std::max(1, c.xcds)), Knobs{c.eps});
     } else {
-        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m, r,
-                           uint32_t(std::max(1, c.xcds)));
+        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, false>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m,
+                           r, uint32_t(std::max(1, c.xcds)), Knobs{0.0f});
     }
 }
 
