@@ -48,6 +48,11 @@ def parse():
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 one lane per ray, 2 persistent")
     ap.add_argument("--refill", type=int, default=0, help="persistent refill threshold (0 = default)")
     ap.add_argument("--ao", type=int, default=8, help="AO rays per primary hit")
+    ap.add_argument("--sort", type=int, default=0, help="ray binning: 0 auto, 1 off, 2 on")
+    ap.add_argument("--sort-chunk", type=int, default=0, help="log2 rays per binning chunk (0 = default)")
+    ap.add_argument("--sort-dirq", type=int, default=0, help="direction bins per axis (0 = default)")
+    ap.add_argument("--sort-cells", type=int, default=0, help="log2 origin cells per axis (0 = default)")
+    ap.add_argument("--eye", default="", help="camera position x,y,z (default: the workload's)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-stride", type=int, default=4,
                     help="oracle sample: every n-th primary ray and the AO rays of its hits")
@@ -84,6 +89,8 @@ def main():
 
     t0 = time.time()
     m, eye, W, H = workload(args.workload)
+    if args.eye:
+        eye = tuple(float(v) for v in args.eye.split(","))
     log("mesh: %d tets, %d points (%.1f s)" % (m.n_tets, m.n_points, time.time() - t0))
     t0 = time.time()
     mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, sfc=args.sfc, layout=args.layout)
@@ -131,7 +138,9 @@ def main():
              "t": torch.empty(n_a, dtype=torch.float32, device=dev),
              "bary": torch.empty((n_a, 2), dtype=torch.float32, device=dev)}
 
-    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill)
+    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill, sort=args.sort,
+              sort_chunk_log2=args.sort_chunk, sort_dirq=args.sort_dirq,
+              sort_cells_log2=args.sort_cells)
 
     def step():
         mesh.trace_into(out_p, po, pd, **kw)
@@ -195,6 +204,7 @@ def main():
             ("row-major" if args.tile <= 1 else "%dx%d tiles" % (args.tile, args.tile)),
             "layout": args.layout, "sfc": args.sfc, "block": args.block,
             "kernel": {0: "auto", 1: "one lane per ray", 2: "persistent lanes"}[args.kernel],
+            "ray_binning": {0: "auto", 1: "off", 2: "on"}[args.sort], "eye": list(eye),
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -73,6 +73,24 @@ struct SortCfg {
 };
 
 int64_t sort_workspace_bytes(int64_t n);
+
+// One job of a batched launch: a mesh, its rays, and where its blocks and
+// binning chunks start in the launch.  Lives in device memory.
+struct Job {
+    DevMesh m;
+    RayArgs r;
+    SortCfg sc;
+    int64_t block0;           // first block of this job in the trace launch
+    int64_t chunk0;           // first chunk of this job in the binning launch
+};
+
+// One launch over all jobs (table in device memory, block0 ascending); jobs
+// share the record layout.  Rays without tmax get +inf.
+hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_blocks, int32_t block,
+                              int32_t layout, hipStream_t s);
+// Binning of every job's rays (chunks of 2^chunk_log2; perm pointers in the table).
+hipError_t launch_sort_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_chunks,
+                             int32_t chunk_log2, hipStream_t s);
 // Fills the permutation (inside ws) that orders the rays by bin.
 hipError_t launch_sort(const SortCfg& c, const float* orig, const float* dir, int64_t n, void* ws,
                        int32_t** perm_out, hipStream_t s);

@@ -54,14 +54,14 @@ __device__ __forceinline__ uint32_t ray_key(const SortCfg& c, float ox, float oy
     return (dirbin << kMinorBits) | (cell & ((1u << kMinorBits) - 1u));
 }
 
+// Counting sort of one chunk (rays base .. base + 2^CHUNK_LOG2 - 1) by key.
 template <int CHUNK_LOG2>
-__global__ void __launch_bounds__(256) k_chunk_sort(SortCfg c, const float* orig, const float* dir,
-                                                    int64_t n, int32_t* perm) {
+__device__ void sort_chunk(const SortCfg& c, const float* orig, const float* dir, int64_t n,
+                           int32_t* perm, int64_t base) {
     constexpr int C = 1 << CHUNK_LOG2;
     constexpr int K = 64 << kMinorBits;            // dirq <= 4
     __shared__ uint32_t hist[K];
     __shared__ uint16_t keys[C];
-    const int64_t base = int64_t(blockIdx.x) * C;
     const int cnt = int(min<int64_t>(C, n - base));
     const int nb = c.dirq * c.dirq * c.dirq << kMinorBits;
     for (int k = threadIdx.x; k < K; k += 256) hist[k] = 0u;
@@ -107,6 +107,29 @@ __global__ void __launch_bounds__(256) k_chunk_sort(SortCfg c, const float* orig
     }
 }
 
+template <int CHUNK_LOG2>
+__global__ void __launch_bounds__(256) k_chunk_sort(SortCfg c, const float* orig, const float* dir,
+                                                    int64_t n, int32_t* perm) {
+    sort_chunk<CHUNK_LOG2>(c, orig, dir, n, perm, int64_t(blockIdx.x) << CHUNK_LOG2);
+}
+
+// Batched: chunk b belongs to the job whose chunk range holds it.
+template <int CHUNK_LOG2>
+__global__ void __launch_bounds__(256) k_chunk_sort_batch(const Job* __restrict__ jobs, int32_t n_jobs) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jobs[mid].chunk0 <= b) lo = mid; else hi = mid;
+    }
+    const RayArgs r = jobs[lo].r;
+    if (!r.perm) return;
+    const SortCfg c = jobs[lo].sc;
+    const int64_t base = (b - jobs[lo].chunk0) << CHUNK_LOG2;
+    if (base >= r.n) return;
+    sort_chunk<CHUNK_LOG2>(c, r.orig, r.dir, r.n, const_cast<int32_t*>(r.perm), base);
+}
+
 }  // namespace
 
 int64_t sort_workspace_bytes(int64_t n) { return (4 * n + 255) / 256 * 256; }
@@ -123,6 +146,19 @@ hipError_t launch_sort(const SortCfg& c, const float* orig, const float* dir, in
         default: hipLaunchKernelGGL(k_chunk_sort<13>, dim3(grid), dim3(256), 0, s, c, orig, dir, n, perm); break;
     }
     *perm_out = perm;
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_chunks,
+                             int32_t chunk_log2, hipStream_t s) {
+    if (total_chunks <= 0 || n_jobs <= 0) return hipSuccess;
+    const dim3 g{unsigned(total_chunks)}, b{256u};
+    switch (chunk_log2) {
+        case 10: hipLaunchKernelGGL(k_chunk_sort_batch<10>, g, b, 0, s, d_jobs, n_jobs); break;
+        case 11: hipLaunchKernelGGL(k_chunk_sort_batch<11>, g, b, 0, s, d_jobs, n_jobs); break;
+        case 12: hipLaunchKernelGGL(k_chunk_sort_batch<12>, g, b, 0, s, d_jobs, n_jobs); break;
+        default: hipLaunchKernelGGL(k_chunk_sort_batch<13>, g, b, 0, s, d_jobs, n_jobs); break;
+    }
     return hipGetLastError();
 }
 

@@ -507,7 +507,7 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
                           float eps) {
     const float ox = r.orig[3 * i], oy = r.orig[3 * i + 1], oz = r.orig[3 * i + 2];
     const float dx = r.dir[3 * i], dy = r.dir[3 * i + 1], dz = r.dir[3 * i + 2];
-    s.tmax = TMAX ? r.tmax[i] : INFINITY;
+    s.tmax = (TMAX && r.tmax) ? r.tmax[i] : INFINITY;
     s.steps = 0;
     const float dd = dx * dx + dy * dy + dz * dz;
     if (!(dd > 0.0f) || !isfinite(dd) || !isfinite(ox + oy + oz) || isnan(s.tmax)) {
@@ -696,6 +696,34 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
     }
 }
 
+// Batched launch: block b belongs to the job whose block range holds it (a
+// binary search that every lane of the block takes alike, so the job's
+// descriptors are read with scalar loads); the rest is the walk of k_trace.
+template <int LAYOUT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jobs[mid].block0 <= b) lo = mid; else hi = mid;
+    }
+    const DevMesh m = jobs[lo].m;
+    const RayArgs r = jobs[lo].r;
+    const int64_t j = (b - jobs[lo].block0) * blockDim.x + threadIdx.x;
+    if (j >= r.n) return;
+    const int64_t i = r.perm ? int64_t(r.perm[j]) : j;
+    const Mem M = make_mem<LAYOUT>(m);
+    Ray s;
+    if (!setup_ray<true, LAYOUT, false>(m, M, r, i, s, 0.0f)) return;
+    Prec pc{0.0f, 0.0f, 0.0f, 0.0f, 0};
+    while (walk_on<true>(s, r.max_steps)) {
+        walk_step<true, LAYOUT, false>(M, s.f, s.g, s.w, pc);
+        ++s.steps;
+    }
+    finish_ray<true>(m, M, r, i, s, 0);
+}
+
 template <int LAYOUT>
 __global__ void __launch_bounds__(256) k_locate(DevMesh m, int64_t n, const float* pts, int32_t* out,
                                                 int32_t max_steps) {
@@ -746,6 +774,19 @@ hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, 
         if (r.tmax) launch_trace_t<true, kTet20>(m, r, c, s);
         else launch_trace_t<false, kTet20>(m, r, c, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_blocks, int32_t block,
+                              int32_t layout, hipStream_t s) {
+    if (total_blocks <= 0 || n_jobs <= 0) return hipSuccess;
+    const dim3 g{unsigned(total_blocks)}, b{unsigned(block)};
+    if (layout == kTet16)
+        hipLaunchKernelGGL(k_trace_batch<kTet16>, g, b, 0, s, d_jobs, n_jobs);
+    else if (layout == kTet32N)
+        hipLaunchKernelGGL(k_trace_batch<kTet32N>, g, b, 0, s, d_jobs, n_jobs);
+    else
+        hipLaunchKernelGGL(k_trace_batch<kTet20>, g, b, 0, s, d_jobs, n_jobs);
     return hipGetLastError();
 }
 
