@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "tiny", "batch64"],
+                    help="batch64: 64 uneven meshes in one batched launch (prints its own line)")
+    ap.add_argument("--batch-meshes", type=int, default=64, help="batch64: number of meshes")
     ap.add_argument("--tile", type=int, default=8, help="pixel tile edge for ray order (1 = row-major)")
     ap.add_argument("--sfc", default="hilbert", choices=["hilbert", "morton", "none"])
     ap.add_argument("--layout", default="tet16", choices=["tet20", "tet16", "tet32n"])
@@ -86,6 +88,8 @@ def main():
         raise RuntimeError("bench.py needs a HIP device")
     dev = torch.device("cuda:0")
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    if args.workload == "batch64":
+        return bench_batch(args, tetrt, dev, log)
 
     t0 = time.time()
     m, eye, W, H = workload(args.workload)
@@ -232,6 +236,102 @@ def main():
         line["cpu_baseline"] = cpu_baseline(m, o, d, ao, ad, atm, sf, parent, hit, args.cpu_stride, log)
     mesh.free()
     print(json.dumps(line), flush=True)
+
+
+def bench_batch(args, tetrt, dev, log):
+    """Many-mesh workload: ``--batch-meshes`` Kuhn meshes, n log-uniform in [8, 96],
+    1..10 spheres each, 1K..1M rays each (half primary from an interior camera,
+    half AO from their hits).  Times the meshes traced one launch each, one
+    batched launch, the batched launch as a HIP graph, and the autotuned batch."""
+    import numpy as np
+    import torch
+    from synth.batch import batch_specs, spec_mesh, camera_rays, ao_from_hits
+
+    specs = batch_specs(count=args.batch_meshes, seed=10)
+    meshes, jobs, total_tets = [], [], 0
+    t0 = time.time()
+    for k, spec in enumerate(specs):
+        m = spec_mesh(spec)
+        mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=args.layout, sfc=args.sfc)
+        total_tets += m.n_tets
+        po, pd = camera_rays(spec)
+        res = mesh.trace(torch.from_numpy(po).to(dev), torch.from_numpy(pd).to(dev))
+        tri = res["tri"].cpu().numpy()
+        tp = res["t"].cpu().numpy()
+        ao, ad, atm, sf = ao_from_hits(m.points, mesh.tri_vertices, po, pd, tri, tp,
+                                       spec["rays"] - len(po), spec["ao_seed"])
+        o = np.concatenate([po, ao])
+        d = np.concatenate([pd, ad])
+        tmax = np.concatenate([np.full(len(po), np.inf, np.float32), atm])
+        sfc = np.concatenate([np.full(len(po), -1, np.int32), sf])
+        n = len(o)
+        jobs.append(dict(mesh=mesh, orig=torch.from_numpy(o).to(dev), dirs=torch.from_numpy(d).to(dev),
+                         tmax=torch.from_numpy(tmax).to(dev), start_face=torch.from_numpy(sfc).to(dev),
+                         out=tetrt.outputs(n, dev)))
+        meshes.append(mesh)
+        log("mesh %d/%d: n=%d, %d tets, %d rays (%d AO)  [%.0f s]" % (
+            k + 1, len(specs), spec["n"], m.n_tets, n, len(ao), time.time() - t0))
+        del m
+    rays = sum(int(j["orig"].shape[0]) for j in jobs)
+    kw = dict(block=args.block, sort=args.sort, sort_chunk_log2=args.sort_chunk,
+              sort_dirq=args.sort_dirq, sort_cells_log2=args.sort_cells)
+    sep_out = [tetrt.outputs(int(j["orig"].shape[0]), dev) for j in jobs]
+
+    def separate():
+        for j, out in zip(jobs, sep_out):
+            j["mesh"].trace_into(out, j["orig"], j["dirs"], tmax=j["tmax"], start_face=j["start_face"], **kw)
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=rays)
+    b.set(jobs, **kw)
+    K = args.steps
+    ms_sep = timed(separate, K)
+    ms_batch = timed(b.launch, K)
+    ms_graph = timed(b.graph_launch, K)
+    chosen, _ = b.tune(reps=3)
+    ms_tuned = timed(b.launch, K)
+    ms_tuned_graph = timed(b.graph_launch, K)
+    torch.cuda.synchronize()
+    # the batched results are those of the separate launches, bit for bit
+    mism = 0
+    for j, out in zip(jobs, sep_out):
+        for key in ("tri", "t", "bary"):
+            x, y = j["out"][key], out[key]
+            mism += int((~((x == y) | (torch.isnan(x) & torch.isnan(y)))).sum().item())
+    best = min(ms_batch, ms_graph, ms_tuned, ms_tuned_graph)
+    line = {
+        "metric": "batched closest-hit Mrays/s over %d meshes" % len(jobs),
+        "value": round(rays / (best * 1e-3) / 1e6, 2),
+        "unit": "Mrays/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(best, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%d Kuhn meshes n log-uniform 8..96, 1-10 spheres, 1K-1M rays each "
+                               "(half primary, half AO)" % len(jobs),
+                   "tets": total_tets, "rays": rays, "layout": args.layout, "tuned": chosen},
+        "detail": {"separate_launches_ms": round(ms_sep, 4), "batch_ms": round(ms_batch, 4),
+                   "batch_graph_ms": round(ms_graph, 4), "tuned_ms": round(ms_tuned, 4),
+                   "tuned_graph_ms": round(ms_tuned_graph, 4),
+                   "separate_mrays_s": round(rays / (ms_sep * 1e-3) / 1e6, 2),
+                   "batch_vs_separate": round(ms_sep / best, 3),
+                   "mismatches_vs_separate": mism},
+    }
+    b.free()
+    for mesh in meshes:
+        mesh.free()
+    print(json.dumps(line), flush=True)
+    if mism:
+        raise SystemExit("batched results differ from separate launches in %d values" % mism)
 
 
 def cpu_baseline(m, o, d, ao, ad, atm, sf, parent, hit, stride, log):

@@ -228,6 +228,196 @@ int tetmesh_locate(tm_mesh m, int64_t n, const float* d_pts, int32_t* d_tet, voi
 int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_present,
                             const tm_trace_opts* opts, int64_t* bytes);
 
+/*
+ * Batched traces over many meshes in one launch.
+ *
+ * A batch holds a table of jobs, each a mesh handle and its rays with the
+ * arrays trace_closest takes.  One launch walks every ray of every job: the
+ * blocks of the launch are split among the jobs in table order, each block
+ * finds its job in the table, and the walk is that of trace_closest with one
+ * lane per ray.  Small meshes thereby share the device with large ones without
+ * a launch, and a host round trip, per mesh.  The results of a ray are those
+ * that trace_closest gives it with the same max_steps.
+ */
+typedef struct {
+    tm_mesh mesh;             /* uploaded on the batch's device; all jobs of a batch share
+                                 one record layout; must outlive every launch of the job */
+    int64_t n_rays;           /* 0 <= n_rays < 2^31 */
+    const float* d_orig;      /* the arrays of trace_closest, same meaning, same rules */
+    const float* d_dir;
+    const float* d_tmax;      /* nullable */
+    const int32_t* d_start_tet;  /* nullable */
+    const int32_t* d_start_face; /* nullable */
+    int32_t* d_tri;
+    float* d_t;
+    float* d_bary;
+    int32_t* d_hit_tets;      /* nullable */
+    int32_t* d_steps;         /* nullable */
+} tm_job;
+
+typedef struct tm_batch_s* tm_batch;
+
+/* tm_batch_create -- a batch on the current HIP device for up to max_jobs jobs
+ * (1..65536) of at most max_rays rays in total (0 <= max_rays < 2^40).  Allocates
+ * the device job table, a pinned host staging copy of it, and the binning
+ * workspace (4 bytes per ray), once.  out host.  Errors: TM_ERR_ARG,
+ * TM_ERR_OOM, TM_ERR_HIP. */
+int tm_batch_create(int32_t max_jobs, int64_t max_rays, tm_batch* out);
+
+/* tm_batch_set -- replace the batch's jobs.  jobs host [n_jobs] (0 <= n_jobs <=
+ * max_jobs), copied.  opts as for trace_closest, except: kernel 0 or 1, eps = 0,
+ * xcds, refill, grid_cap, workspace and fp64_steps are ignored, and the binning
+ * chunk size is one for all jobs (sort = 0 bins the jobs that carry tmax and
+ * have at least 2^18 rays).  The new table is copied to the device on
+ * hip_stream, after the batch's previous table copy has left the staging
+ * buffer; launches on that stream that follow see it.  A launch of the batch on
+ * another stream must be ordered after this call's stream by the caller.
+ * Errors: TM_ERR_ARG (the first offending job is named), TM_ERR_HIP. */
+int tm_batch_set(tm_batch b, int32_t n_jobs, const tm_job* jobs, const tm_trace_opts* opts,
+                 void* hip_stream);
+
+/* tm_batch_launch -- enqueue the walk of every ray of every job on hip_stream:
+ * at most two kernel launches (binning, walk), with no allocation, memory set,
+ * copy or synchronisation, so a caller may capture it into a HIP graph.
+ * Errors: TM_ERR_ARG, TM_ERR_HIP. */
+int tm_batch_launch(tm_batch b, void* hip_stream);
+
+/* tm_batch_graph_launch -- tm_batch_launch as a HIP graph owned by the batch.
+ * The graph is captured on first use and again whenever tm_batch_set changed
+ * the launch shape (blocks, chunks, block size); otherwise a replay costs one
+ * graph launch.  Job contents may change between replays through tm_batch_set.
+ * Errors: TM_ERR_ARG, TM_ERR_HIP. */
+int tm_batch_graph_launch(tm_batch b, void* hip_stream);
+
+/* tm_batch_tune -- autotuner: times tm_batch_launch on the current jobs for
+ * each block size (64, 128, 256) and binning setting (off; on with 2^11, 2^12,
+ * 2^13 rays per chunk), reps timed launches each after one warm-up, with HIP
+ * events on hip_stream, and keeps the fastest.  Overwrites the jobs' outputs
+ * (with the same results).  Synchronous.  chosen host, nullable: receives the
+ * options kept; ms host, nullable: their mean launch time in milliseconds.
+ * Errors: TM_ERR_ARG, TM_ERR_HIP. */
+int tm_batch_tune(tm_batch b, int32_t reps, void* hip_stream, tm_trace_opts* chosen, float* ms);
+
+/* tm_batch_free -- release the batch (synchronises the device first).  NULL is
+ * a no-op.  The meshes of its jobs are not freed. */
+int tm_batch_free(tm_batch b);
+
+/*
+ * Serving: requests against resident meshes, batched continuously.
+ *
+ * A request renders one image of one mesh: a camera ray per pixel (pinhole,
+ * as in the paper's renderer), and for shadow and ambient-occlusion requests
+ * one more ray per pixel from the camera ray's hit (paper, Sec. "Handling
+ * Common Ray-tracing Operations": secondary rays start from the hit face).
+ * The server admits queued requests while their rays fit a preallocated ray
+ * pool, generates rays on the device, and at each step traces the pending
+ * phase of every admitted request in one batched launch (tm_batch), so work
+ * of different requests and meshes shares the device.  Up to `ring` launches
+ * are in flight; a step never waits for the device.  A server is driven by one
+ * host thread.
+ *
+ * Results are written to the request's own device buffers, one entry per
+ * pixel in tile order: 8x8 pixel tiles, tiles row-major over the image, pixels
+ * row-major inside a tile (ray k is pixel (8 (tile % (W/8)) + k % 8,
+ * 8 (tile / (W/8)) + (k % 64) / 8) with tile = k / 64).
+ *   TM_REQ_PRIMARY: the camera ray's trace_closest results.
+ *   TM_REQ_SHADOW:  the results of the ray from the hit point P towards the
+ *                   light L (direction L - P, tmax 1): a triangle id = in
+ *                   shadow, TM_RAY_MISS = lit; TM_RAY_INVALID where the camera
+ *                   ray hit nothing.
+ *   TM_REQ_AO:      the results of one cosine-weighted ray (tmax ao_tmax) about
+ *                   the hit triangle's normal, on the side the camera ray came
+ *                   from; TM_RAY_INVALID where the camera ray hit nothing.
+ * A request's results depend on the request alone, not on what it was batched with.
+ */
+enum { TM_REQ_PRIMARY = 0, TM_REQ_SHADOW = 1, TM_REQ_AO = 2 };
+
+typedef struct {
+    int32_t mesh;        /* index into the meshes given to tm_server_create */
+    int32_t kind;        /* TM_REQ_* */
+    int32_t width;       /* image size, multiples of 8 in [8, 8192] */
+    int32_t height;
+    float eye[3];        /* camera position */
+    float forward[3];    /* view direction, nonzero */
+    float up[3];         /* up hint, not parallel to forward */
+    float fov_h_deg;     /* horizontal field of view, in (0, 179] degrees */
+    float light[3];      /* TM_REQ_SHADOW: point light */
+    float ao_tmax;       /* TM_REQ_AO: ray length (> 0) */
+    uint32_t seed;       /* TM_REQ_AO: random stream of the directions */
+    int32_t* d_tri;      /* device out [width*height] (caller-owned until the request is done) */
+    float* d_t;          /* device out [width*height] */
+    float* d_bary;       /* device out [width*height][2], 8-byte aligned */
+} tm_request;
+
+typedef struct {
+    int64_t max_rays;     /* ray pool slots (one per pixel of every admitted request),
+                             1 <= max_rays <= 2^31 - 1; 48 bytes of device memory each */
+    int32_t max_requests; /* admitted requests at once, 1..65536 (0 = 4096) */
+    int32_t ring;         /* launches in flight, 1..8 (0 = 3) */
+    int32_t block;        /* as tm_trace_opts */
+    int32_t sort;
+    int32_t max_steps;
+    int32_t reserved;
+} tm_server_opts;
+
+/* A finished request; times are host steady-clock nanoseconds. */
+typedef struct {
+    int64_t id;
+    int64_t submit_ns;   /* tm_server_submit */
+    int64_t admit_ns;    /* admitted to the pool */
+    int64_t done_ns;     /* the step that saw its last launch complete */
+    int64_t rays;        /* rays traced for it */
+} tm_done;
+
+typedef struct tm_server_s* tm_server;
+
+/* tm_server_create -- meshes host [n_meshes] (1..65536 handles, one record
+ * layout, current device; they must outlive the server); opts nullable.
+ * Allocates the ray pool and the launch ring once.  Errors: TM_ERR_ARG,
+ * TM_ERR_OOM, TM_ERR_HIP. */
+int tm_server_create(const tm_mesh* meshes, int32_t n_meshes, const tm_server_opts* opts,
+                     tm_server* out);
+
+/* tm_server_submit -- queue a request (copied; FIFO admission); *id host out (ids
+ * start at 1).  Host only, never blocks.  Errors: TM_ERR_ARG (a request that
+ * could never fit the pool included). */
+int tm_server_submit(tm_server s, const tm_request* req, int64_t* id);
+
+/* tm_server_step -- retire completed launches, admit queued requests that fit,
+ * and enqueue on hip_stream one launch of ray generation and one batched trace
+ * of every pending phase.  Never waits for the device: with the ring full it
+ * launches nothing.  *launched host out, nullable: rays launched.  Use one
+ * stream for every step of a server.  Errors: TM_ERR_ARG, TM_ERR_HIP. */
+int tm_server_step(tm_server s, void* hip_stream, int64_t* launched);
+
+/* tm_server_poll -- move up to max finished requests to out (host [max]); *n
+ * host out.  Their outputs are complete when they are reported. */
+int tm_server_poll(tm_server s, tm_done* out, int32_t max, int32_t* n);
+
+/* tm_server_drain -- step until every submitted request is finished, waiting
+ * on the device between steps.  Errors as tm_server_step. */
+int tm_server_drain(tm_server s, void* hip_stream);
+
+/* tm_server_pending -- requests submitted and not yet reported by poll; host out. */
+int tm_server_pending(tm_server s, int64_t* queued, int64_t* admitted, int64_t* finished);
+
+/* tm_request_rays -- the rays a server generates for a request, written to
+ * caller arrays (for checking results, or tracing them elsewhere).  m: the
+ * request's mesh; req->mesh and the output pointers are ignored.
+ *   phase 0: camera rays -> d_orig, d_dir [W*H][3], d_tmax (+inf), d_start_face (-1).
+ *   phase 1 (shadow, AO): reads the camera rays in d_orig, d_dir and their
+ *            trace_closest results d_tri, d_t [W*H], and overwrites d_orig, d_dir,
+ *            d_tmax, d_start_face with the secondary rays (zero direction where
+ *            d_tri < 0).
+ * All device arrays, tile order as above.  Errors: TM_ERR_ARG, TM_ERR_HIP. */
+int tm_request_rays(tm_mesh m, const tm_request* req, int32_t phase, float* d_orig, float* d_dir,
+                    float* d_tmax, int32_t* d_start_face, const int32_t* d_tri, const float* d_t,
+                    void* hip_stream);
+
+/* tm_server_free -- release the server (synchronises the device first).  NULL
+ * is a no-op. */
+int tm_server_free(tm_server s);
+
 /* tetmesh_tri_vertices -- host: vertex ids (caller numbering, ascending) of
  * triangles.  tri host int32 [n]; out host int32 [n][3].  TM_ERR_ARG on an id
  * out of range. */

@@ -57,6 +57,35 @@ def _trace_opts(kw, workspace=None, fp64_steps=None, n=0):
     return o
 
 
+class _Job(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("n_rays", C.c_int64), ("d_orig", C.c_void_p),
+                ("d_dir", C.c_void_p), ("d_tmax", C.c_void_p), ("d_start_tet", C.c_void_p),
+                ("d_start_face", C.c_void_p), ("d_tri", C.c_void_p), ("d_t", C.c_void_p),
+                ("d_bary", C.c_void_p), ("d_hit_tets", C.c_void_p), ("d_steps", C.c_void_p)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("mesh", C.c_int32), ("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("eye", C.c_float * 3), ("forward", C.c_float * 3), ("up", C.c_float * 3),
+                ("fov_h_deg", C.c_float), ("light", C.c_float * 3), ("ao_tmax", C.c_float),
+                ("seed", C.c_uint32), ("d_tri", C.c_void_p), ("d_t", C.c_void_p), ("d_bary", C.c_void_p)]
+
+
+class _ServerOpts(C.Structure):
+    _fields_ = [("max_rays", C.c_int64), ("max_requests", C.c_int32), ("ring", C.c_int32),
+                ("block", C.c_int32), ("sort", C.c_int32), ("max_steps", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class _Done(C.Structure):
+    _fields_ = [("id", C.c_int64), ("submit_ns", C.c_int64), ("admit_ns", C.c_int64),
+                ("done_ns", C.c_int64), ("rays", C.c_int64)]
+
+
+REQ_PRIMARY, REQ_SHADOW, REQ_AO = 0, 1, 2
+_KINDS = {"primary": 0, "shadow": 1, "ao": 2}
+
+
 class _Info(C.Structure):
     _fields_ = [("n_tets", C.c_int64), ("n_points", C.c_int64), ("n_tris", C.c_int64),
                 ("hot_bytes", C.c_int64), ("cold_bytes", C.c_int64), ("layout", C.c_int32),
@@ -98,6 +127,34 @@ def _load():
     L.tetmesh_free.argtypes = [vp]
     L.tetrt_sfc_keys.restype = C.c_int
     L.tetrt_sfc_keys.argtypes = [i32, i32, i64, vp, vp]
+    L.tm_batch_create.restype = C.c_int
+    L.tm_batch_create.argtypes = [i32, i64, C.POINTER(vp)]
+    L.tm_batch_set.restype = C.c_int
+    L.tm_batch_set.argtypes = [vp, i32, C.POINTER(_Job), C.POINTER(_TraceOpts), vp]
+    L.tm_batch_launch.restype = C.c_int
+    L.tm_batch_launch.argtypes = [vp, vp]
+    L.tm_batch_graph_launch.restype = C.c_int
+    L.tm_batch_graph_launch.argtypes = [vp, vp]
+    L.tm_batch_tune.restype = C.c_int
+    L.tm_batch_tune.argtypes = [vp, i32, vp, C.POINTER(_TraceOpts), C.POINTER(C.c_float)]
+    L.tm_batch_free.restype = C.c_int
+    L.tm_batch_free.argtypes = [vp]
+    L.tm_server_create.restype = C.c_int
+    L.tm_server_create.argtypes = [C.POINTER(vp), i32, C.POINTER(_ServerOpts), C.POINTER(vp)]
+    L.tm_server_submit.restype = C.c_int
+    L.tm_server_submit.argtypes = [vp, C.POINTER(_Request), C.POINTER(i64)]
+    L.tm_server_step.restype = C.c_int
+    L.tm_server_step.argtypes = [vp, vp, C.POINTER(i64)]
+    L.tm_server_poll.restype = C.c_int
+    L.tm_server_poll.argtypes = [vp, C.POINTER(_Done), i32, C.POINTER(i32)]
+    L.tm_server_drain.restype = C.c_int
+    L.tm_server_drain.argtypes = [vp, vp]
+    L.tm_server_pending.restype = C.c_int
+    L.tm_server_pending.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.tm_server_free.restype = C.c_int
+    L.tm_server_free.argtypes = [vp]
+    L.tm_request_rays.restype = C.c_int
+    L.tm_request_rays.argtypes = [vp, C.POINTER(_Request), i32, vp, vp, vp, vp, vp, vp, vp]
     _lib = L
     return L
 
@@ -219,7 +276,152 @@ def tetrt_sfc_keys(xyz, bits=21, curve="hilbert"):
     return out
 
 
-# ---- convenience wrapper --------------------------------------------------------------
+def tm_batch_create(max_jobs, max_rays):
+    h = C.c_void_p()
+    _check(_load().tm_batch_create(int(max_jobs), int(max_rays), C.byref(h)))
+    return h.value
+
+
+def _job(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, start_face=None,
+         hit_tets=None, steps=None):
+    n = int(orig.shape[0])
+    j = _Job()
+    j.mesh = handle
+    j.n_rays = n
+    j.d_orig = _dev(orig, torch.float32, n, (3,), "orig")
+    j.d_dir = _dev(dirs, torch.float32, n, (3,), "dirs")
+    j.d_tmax = _dev(tmax, torch.float32, n, (), "tmax", True)
+    j.d_start_tet = _dev(start_tet, torch.int32, n, (), "start_tet", True)
+    j.d_start_face = _dev(start_face, torch.int32, n, (), "start_face", True)
+    j.d_tri = _dev(tri, torch.int32, n, (), "tri")
+    j.d_t = _dev(t, torch.float32, n, (), "t")
+    j.d_bary = _dev(bary, torch.float32, n, (2,), "bary")
+    j.d_hit_tets = _dev(hit_tets, torch.int32, n, (2,), "hit_tets", True)
+    j.d_steps = _dev(steps, torch.int32, n, (), "steps", True)
+    return j
+
+
+def tm_batch_set(batch, jobs, stream=None, **opts):
+    """``jobs``: sequence of dicts with the keyword arguments of trace_closest
+    (``handle``, ``orig``, ``dirs``, ``tri``, ``t``, ``bary`` and the optional ones)."""
+    arr = (_Job * max(1, len(jobs)))(*[_job(**j) for j in jobs])
+    o = _trace_opts(dict(opts))
+    _check(_load().tm_batch_set(C.c_void_p(batch), len(jobs), arr, C.byref(o), _stream(stream)))
+
+
+def tm_batch_launch(batch, stream=None):
+    _check(_load().tm_batch_launch(C.c_void_p(batch), _stream(stream)))
+
+
+def tm_batch_graph_launch(batch, stream=None):
+    _check(_load().tm_batch_graph_launch(C.c_void_p(batch), _stream(stream)))
+
+
+def tm_batch_tune(batch, reps=5, stream=None):
+    o = _TraceOpts()
+    ms = C.c_float()
+    _check(_load().tm_batch_tune(C.c_void_p(batch), int(reps), _stream(stream), C.byref(o),
+                                 C.byref(ms)))
+    return {k: getattr(o, k) for k in ("block", "sort", "sort_chunk_log2")}, ms.value
+
+
+def tm_batch_free(batch):
+    _check(_load().tm_batch_free(C.c_void_p(batch)))
+
+
+def _request(mesh=0, kind="primary", width=64, height=64, eye=(0.5, 0.5, 0.5),
+             forward=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), fov_h_deg=60.0, light=(0.0, 0.0, 0.0),
+             ao_tmax=0.1, seed=0, out=None):
+    r = _Request()
+    r.mesh = int(mesh)
+    r.kind = _KINDS[kind] if isinstance(kind, str) else int(kind)
+    r.width, r.height = int(width), int(height)
+    r.eye[:] = [float(v) for v in eye]
+    r.forward[:] = [float(v) for v in forward]
+    r.up[:] = [float(v) for v in up]
+    r.fov_h_deg = float(fov_h_deg)
+    r.light[:] = [float(v) for v in light]
+    r.ao_tmax = float(ao_tmax)
+    r.seed = int(seed) & 0xFFFFFFFF
+    if out is not None:
+        n = r.width * r.height
+        r.d_tri = _dev(out["tri"], torch.int32, n, (), "out['tri']")
+        r.d_t = _dev(out["t"], torch.float32, n, (), "out['t']")
+        r.d_bary = _dev(out["bary"], torch.float32, n, (2,), "out['bary']")
+    return r
+
+
+def tm_server_create(handles, max_rays, max_requests=0, ring=0, block=0, sort=0, max_steps=0):
+    arr = (C.c_void_p * len(handles))(*handles)
+    o = _ServerOpts(int(max_rays), int(max_requests), int(ring), int(block), int(sort), int(max_steps), 0)
+    h = C.c_void_p()
+    _check(_load().tm_server_create(arr, len(handles), C.byref(o), C.byref(h)))
+    return h.value
+
+
+def tm_server_submit(server, **req):
+    """``req``: the tm_request fields (mesh, kind, width, height, eye, forward, up,
+    fov_h_deg, light, ao_tmax, seed) and ``out``, a dict of device tensors as from
+    ``outputs(width * height, ...)``.  Returns the request id."""
+    r = _request(**req)
+    i = C.c_int64()
+    _check(_load().tm_server_submit(C.c_void_p(server), C.byref(r), C.byref(i)))
+    return i.value
+
+
+def tm_server_step(server, stream=None):
+    n = C.c_int64()
+    _check(_load().tm_server_step(C.c_void_p(server), _stream(stream), C.byref(n)))
+    return n.value
+
+
+def tm_server_poll(server, max_items=1024):
+    buf = (_Done * max_items)()
+    n = C.c_int32()
+    _check(_load().tm_server_poll(C.c_void_p(server), buf, int(max_items), C.byref(n)))
+    return [{k: getattr(buf[i], k) for k, _ in _Done._fields_} for i in range(n.value)]
+
+
+def tm_server_drain(server, stream=None):
+    _check(_load().tm_server_drain(C.c_void_p(server), _stream(stream)))
+
+
+def tm_server_pending(server):
+    q, a, f = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(_load().tm_server_pending(C.c_void_p(server), C.byref(q), C.byref(a), C.byref(f)))
+    return {"queued": q.value, "admitted": a.value, "finished": f.value}
+
+
+def tm_server_free(server):
+    _check(_load().tm_server_free(C.c_void_p(server)))
+
+
+def tm_request_rays(handle, phase, orig, dirs, tmax, start_face, tri=None, t=None, stream=None, **req):
+    """The rays a server generates for a request (phase 0 camera, phase 1 secondary),
+    written into the given device tensors."""
+    r = _request(**req)
+    n = r.width * r.height
+    _check(_load().tm_request_rays(
+        C.c_void_p(handle), C.byref(r), int(phase), _dev(orig, torch.float32, n, (3,), "orig"),
+        _dev(dirs, torch.float32, n, (3,), "dirs"), _dev(tmax, torch.float32, n, (), "tmax"),
+        _dev(start_face, torch.int32, n, (), "start_face"),
+        _dev(tri, torch.int32, n, (), "tri", True), _dev(t, torch.float32, n, (), "t", True),
+        _stream(stream)))
+
+
+# ---- convenience wrappers -------------------------------------------------------------
+
+def outputs(n, device, want_tets=False, want_steps=False):
+    """Output tensors of a trace of n rays."""
+    out = {"tri": torch.empty(n, dtype=torch.int32, device=device),
+           "t": torch.empty(n, dtype=torch.float32, device=device),
+           "bary": torch.empty((n, 2), dtype=torch.float32, device=device)}
+    if want_tets:
+        out["hit_tets"] = torch.empty((n, 2), dtype=torch.int32, device=device)
+    if want_steps:
+        out["steps"] = torch.empty(n, dtype=torch.int32, device=device)
+    return out
+
 
 class Mesh:
     """An uploaded mesh.  ``trace`` allocates its outputs; ``trace_into`` writes into
@@ -242,13 +444,7 @@ class Mesh:
               want_steps=False, want_fp64=False, workspace=None, stream=None, **opts):
         n = int(orig.shape[0])
         dev = orig.device
-        out = {"tri": torch.empty(n, dtype=torch.int32, device=dev),
-               "t": torch.empty(n, dtype=torch.float32, device=dev),
-               "bary": torch.empty((n, 2), dtype=torch.float32, device=dev)}
-        if want_tets:
-            out["hit_tets"] = torch.empty((n, 2), dtype=torch.int32, device=dev)
-        if want_steps:
-            out["steps"] = torch.empty(n, dtype=torch.int32, device=dev)
+        out = outputs(n, dev, want_tets, want_steps)
         if want_fp64:
             out["fp64_steps"] = torch.empty(n, dtype=torch.int32, device=dev)
         self.trace_into(out, orig, dirs, tmax, start_tet, start_face, workspace, stream, **opts)
@@ -276,3 +472,82 @@ class Mesh:
 
 def upload(points, tets, nbrs, cflag, **kw) -> Mesh:
     return Mesh(tetmesh_upload(points, tets, nbrs, cflag, **kw))
+
+
+class Batch:
+    """Batched traces over many meshes (tm_batch_*).  ``set`` takes a list of jobs,
+    each a dict: ``mesh`` (a Mesh), ``orig``, ``dirs``, ``out`` (a dict as from
+    ``outputs``) and optionally ``tmax``, ``start_tet``, ``start_face``.  The
+    batch keeps references to the tensors of its current jobs."""
+
+    def __init__(self, max_jobs, max_rays):
+        self.handle = tm_batch_create(max_jobs, max_rays)
+        self._jobs = []
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self.handle = None
+            tm_batch_free(h)
+
+    def set(self, jobs, stream=None, **opts):
+        spec = []
+        for j in jobs:
+            out = j["out"]
+            spec.append(dict(handle=j["mesh"].handle, orig=j["orig"], dirs=j["dirs"],
+                             tri=out["tri"], t=out["t"], bary=out["bary"], tmax=j.get("tmax"),
+                             start_tet=j.get("start_tet"), start_face=j.get("start_face"),
+                             hit_tets=out.get("hit_tets"), steps=out.get("steps")))
+        tm_batch_set(self.handle, spec, stream, **opts)
+        self._jobs = list(jobs)
+
+    def launch(self, stream=None):
+        tm_batch_launch(self.handle, stream)
+
+    def graph_launch(self, stream=None):
+        tm_batch_graph_launch(self.handle, stream)
+
+    def tune(self, reps=5, stream=None):
+        return tm_batch_tune(self.handle, reps, stream)
+
+
+class Server:
+    """Serving loop over resident meshes (tm_server_*).  ``submit`` keeps the
+    request's output tensors alive until ``poll`` reports it."""
+
+    def __init__(self, meshes, max_rays, **opts):
+        self.meshes = list(meshes)
+        self.handle = tm_server_create([m.handle for m in self.meshes], max_rays, **opts)
+        self._outs = {}
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self.handle = None
+            tm_server_free(h)
+
+    def submit(self, out, **req):
+        i = tm_server_submit(self.handle, out=out, **req)
+        self._outs[i] = out
+        return i
+
+    def step(self, stream=None):
+        return tm_server_step(self.handle, stream)
+
+    def poll(self, max_items=1024):
+        done = tm_server_poll(self.handle, max_items)
+        for d in done:
+            self._outs.pop(d["id"], None)
+        return done
+
+    def drain(self, stream=None):
+        tm_server_drain(self.handle, stream)
+
+    def pending(self):
+        return tm_server_pending(self.handle)

@@ -7,8 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtetrt.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("api.cpp", "pack.cpp", "walk.hip", "sort.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("pack.h", "device.h")] + [
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("api.cpp", "batch.cpp", "server.cpp", "pack.cpp", "walk.hip", "sort.hip", "serve.hip")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("pack.h", "device.h", "handle.h")] + [
     os.path.join(ROOT, "include", "tetrt.h")]
 
 HIPCC_FLAGS = [

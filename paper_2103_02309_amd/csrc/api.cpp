@@ -11,27 +11,19 @@
 #include <vector>
 
 #include "device.h"
+#include "handle.h"
 #include "pack.h"
 #include "tetrt.h"
 
-struct tm_mesh_s {
-    tetrt::DevMesh dev{};
-    int device = 0;
-    int cus = 0;
-    int64_t np = 0, nt = 0, ntri = 0;
-    int32_t layout = 0, sfc = 0;
-    int64_t hot_bytes = 0, cold_bytes = 0;
-    std::vector<int32_t> tri_verts_user;  // host copy for tetmesh_tri_vertices
-    std::vector<void*> allocations;
-    float lo[3] = {0, 0, 0}, ext[3] = {0, 0, 0};  // bounds of the points
-    std::mutex ws_mu;                   // the handle's workspace for ray binning
-    void* ws = nullptr;
-    int64_t ws_bytes = 0;
-};
+namespace tetrt {
 
 namespace {
-
 thread_local std::string g_error;
+}  // namespace
+
+void clear_error() { g_error.clear(); }
+
+const char* last_error() { return g_error.c_str(); }
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -45,14 +37,6 @@ int fail(int code, const char* fmt, ...) {
 
 int hip_fail(hipError_t e, const char* what) {
     return fail(TM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-void release(tm_mesh_s* m) {
-    for (void* p : m->allocations) (void)hipFree(p);
-    m->allocations.clear();
-    if (m->ws) (void)hipFree(m->ws);
-    m->ws = nullptr;
-    m->ws_bytes = 0;
 }
 
 // Binning configuration of a trace; *on = false when the rays are not binned.
@@ -73,6 +57,22 @@ int sort_config(const tm_mesh_s* m, const tm_trace_opts& o, int64_t n, bool has_
         c->inv[a] = m->ext[a] > 0 ? float(G / m->ext[a]) : 0.0f;
     }
     return TM_OK;
+}
+
+}  // namespace tetrt
+
+namespace {
+
+using tetrt::fail;
+using tetrt::hip_fail;
+using tetrt::sort_config;
+
+void release(tm_mesh_s* m) {
+    for (void* p : m->allocations) (void)hipFree(p);
+    m->allocations.clear();
+    if (m->ws) (void)hipFree(m->ws);
+    m->ws = nullptr;
+    m->ws_bytes = 0;
 }
 
 // Copy a host vector into a new device buffer owned by the handle.
@@ -99,11 +99,11 @@ int upload_array(tm_mesh_s* m, const std::vector<T>& v, const T** out, int64_t* 
 
 extern "C" {
 
-const char* tm_last_error(void) { return g_error.c_str(); }
+const char* tm_last_error(void) { return tetrt::last_error(); }
 
 int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, const int32_t* nbrs,
                    const uint8_t* cflag, int64_t n_tets, const tm_upload_opts* opts, tm_mesh* out) {
-    g_error.clear();
+    tetrt::clear_error();
     if (!out) return fail(TM_ERR_ARG, "tetmesh_upload: out is NULL");
     *out = nullptr;
     if (!points || !tets || !nbrs || !cflag)
@@ -197,7 +197,7 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
                   const float* d_tmax, const int32_t* d_start_tet, const int32_t* d_start_face,
                   int32_t* d_tri, float* d_t, float* d_bary, int32_t* d_hit_tets, int32_t* d_steps,
                   const tm_trace_opts* opts, void* hip_stream) {
-    g_error.clear();
+    tetrt::clear_error();
     if (!m) return fail(TM_ERR_ARG, "trace_closest: NULL mesh");
     if (n_rays < 0 || n_rays > int64_t(0x7FFFFFFF))
         return fail(TM_ERR_ARG, "trace_closest: n_rays = %lld out of range [0, 2^31)",
@@ -303,7 +303,7 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
 
 int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_present,
                             const tm_trace_opts* opts, int64_t* bytes) {
-    g_error.clear();
+    tetrt::clear_error();
     if (!m || !bytes) return fail(TM_ERR_ARG, "tetmesh_trace_workspace: NULL argument");
     if (n_rays < 0 || n_rays > int64_t(0x7FFFFFFF))
         return fail(TM_ERR_ARG, "tetmesh_trace_workspace: n_rays out of range");
@@ -319,7 +319,7 @@ int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_prese
 }
 
 int tetmesh_locate(tm_mesh m, int64_t n, const float* d_pts, int32_t* d_tet, void* hip_stream) {
-    g_error.clear();
+    tetrt::clear_error();
     if (!m) return fail(TM_ERR_ARG, "tetmesh_locate: NULL mesh");
     if (n < 0 || n > int64_t(0x7FFFFFFF))
         return fail(TM_ERR_ARG, "tetmesh_locate: n = %lld out of range [0, 2^31)", (long long)n);
@@ -332,7 +332,7 @@ int tetmesh_locate(tm_mesh m, int64_t n, const float* d_pts, int32_t* d_tet, voi
 }
 
 int tetmesh_tri_vertices(tm_mesh m, int64_t n, const int32_t* tri, int32_t* out) {
-    g_error.clear();
+    tetrt::clear_error();
     if (!m) return fail(TM_ERR_ARG, "tetmesh_tri_vertices: NULL mesh");
     if (n < 0) return fail(TM_ERR_ARG, "tetmesh_tri_vertices: negative n");
     if (n > 0 && (!tri || !out)) return fail(TM_ERR_ARG, "tetmesh_tri_vertices: NULL array");
@@ -345,7 +345,7 @@ int tetmesh_tri_vertices(tm_mesh m, int64_t n, const int32_t* tri, int32_t* out)
 }
 
 int tetmesh_info(tm_mesh m, tm_info* out) {
-    g_error.clear();
+    tetrt::clear_error();
     if (!m || !out) return fail(TM_ERR_ARG, "tetmesh_info: NULL argument");
     out->n_tets = m->nt;
     out->n_points = m->np;
@@ -360,7 +360,7 @@ int tetmesh_info(tm_mesh m, tm_info* out) {
 }
 
 int tetmesh_free(tm_mesh m) {
-    g_error.clear();
+    tetrt::clear_error();
     if (!m) return TM_OK;
     int prev = 0;
     (void)hipGetDevice(&prev);
@@ -374,7 +374,7 @@ int tetmesh_free(tm_mesh m) {
 }
 
 int tetrt_sfc_keys(int32_t curve, int32_t bits, int64_t n, const uint32_t* xyz, uint64_t* out) {
-    g_error.clear();
+    tetrt::clear_error();
     if (bits < 1 || bits > 21) return fail(TM_ERR_ARG, "tetrt_sfc_keys: bits must be in [1, 21]");
     if (curve != TM_SFC_HILBERT && curve != TM_SFC_MORTON)
         return fail(TM_ERR_ARG, "tetrt_sfc_keys: unknown curve %d", curve);

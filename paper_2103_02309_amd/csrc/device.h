@@ -97,4 +97,40 @@ hipError_t launch_sort(const SortCfg& c, const float* orig, const float* dir, in
 hipError_t launch_locate(const DevMesh& m, int64_t n, const float* pts, int32_t* out,
                          int32_t max_steps, hipStream_t s);
 
+// Ray generation for served requests.  The ray slots of a request are a range of
+// a pool; phase 0 writes camera rays, phase 1 turns each slot's phase-0 ray and
+// its hit (tri, t) into a shadow or ambient-occlusion ray in place.
+struct RayPool {
+    float* orig;       // [cap][3]
+    float* dir;        // [cap][3]
+    float* tmax;       // [cap]
+    int32_t* sf;       // [cap] start face
+    int32_t* tri;      // [cap] phase-0 results
+    float* t;          // [cap]
+    float* bary;       // [cap][2]
+};
+
+enum GenKind : int32_t { kGenCamera = 0, kGenShadow = 1, kGenAO = 2 };
+constexpr int kGenBlock = 256;   // threads per block of the generation launch
+
+struct GenEntry {
+    int32_t kind;      // GenKind
+    int32_t W, H;      // image size, multiples of 8; rays in 8x8 tiles, tiles row-major
+    uint32_t seed;     // AO random stream
+    int64_t block0;    // first block of this entry in the launch
+    int64_t base;      // first pool slot
+    float eye[3];
+    float fwd[3];      // camera: unit forward, and right / up scaled by the half-extent
+    float right[3];    //   of the image plane at distance 1
+    float up[3];
+    float light[3];    // shadow: light position
+    float ao_tmax;
+    const float* pts;  // mesh points (float4) and constrained-face vertices (int4),
+    const int32_t* cfv;//   for the normal of the hit triangle
+};
+
+hipError_t launch_gen(const GenEntry* d_gen, int32_t n, int64_t total_blocks, RayPool pool, hipStream_t s);
+// The rays of one entry (base = 0 into the given arrays).
+hipError_t launch_gen_one(const GenEntry& g, RayPool pool, hipStream_t s);
+
 }  // namespace tetrt

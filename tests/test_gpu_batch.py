@@ -1,0 +1,217 @@
+"""Batched traces over many meshes (tm_batch_*): every job's results equal those
+of trace_closest on its own mesh, bit for bit, and agree with the FP64 oracle;
+binning, block sizes, graph replays, job-table updates and the autotuner leave
+them unchanged."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from oracle.compare import compare
+from synth.batch import batch_specs, spec_mesh, camera_rays, ao_from_hits
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("tri", "t", "bary", "hit_tets", "steps")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _host(res):
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in res.items()}
+
+
+@pytest.fixture(scope="module")
+def tetrt():
+    import paper_2103_02309_amd as tetrt
+    return tetrt
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    """Ten uneven meshes (n 4..20) with mixed primary + AO rays (AO from oracle hits)."""
+    out = []
+    for spec in batch_specs(count=10, seed=21, n_lo=4, n_hi=20, rays_lo=200, rays_hi=30_000):
+        m = spec_mesh(spec)
+        om = oracle.OracleMesh.from_kuhn(m)
+        po, pd = camera_rays(spec)
+        pref = om.trace(po, pd)
+        ao, ad, atm, sf = ao_from_hits(m.points, lambda ids: om.tri_verts[ids], po, pd, pref["tri"],
+                                       pref["t"], spec["rays"] - len(po), spec["ao_seed"])
+        o = np.concatenate([po, ao])
+        d = np.concatenate([pd, ad])
+        tmax = np.concatenate([np.full(len(po), np.inf, np.float32), atm])
+        sfc = np.concatenate([np.full(len(po), -1, np.int32), sf])
+        out.append(dict(spec=spec, mesh=m, oracle=om, o=o, d=d, tmax=tmax, sf=sfc))
+    return out
+
+
+@pytest.fixture(scope="module", params=["tet16", "tet20"])
+def uploaded(request, tetrt, scenes):
+    meshes = [tetrt.upload(s["mesh"].points, s["mesh"].tets, s["mesh"].nbrs, s["mesh"].cflag,
+                           layout=request.param) for s in scenes]
+    yield meshes
+    for m in meshes:
+        m.free()
+
+
+def _jobs(tetrt, scenes, meshes, empty_at=(3,), reverse=False):
+    jobs = []
+    for k, (s, mesh) in enumerate(zip(scenes, meshes)):
+        if k in empty_at:
+            z = torch.zeros((0, 3), dtype=torch.float32, device="cuda:0")
+            jobs.append(dict(mesh=mesh, orig=z, dirs=z.clone(),
+                             out=tetrt.outputs(0, "cuda:0", True, True)))
+        sel = slice(None, None, -1) if reverse else slice(None)
+        n = len(s["o"])
+        jobs.append(dict(mesh=mesh, orig=_dev(s["o"][sel]), dirs=_dev(s["d"][sel]),
+                         tmax=_dev(s["tmax"][sel]), start_face=_dev(s["sf"][sel]),
+                         out=tetrt.outputs(n, "cuda:0", True, True)))
+    z = torch.zeros((0, 3), dtype=torch.float32, device="cuda:0")
+    jobs.append(dict(mesh=meshes[0], orig=z, dirs=z.clone(), out=tetrt.outputs(0, "cuda:0", True, True)))
+    return jobs
+
+
+def _single(job):
+    """The same rays through trace_closest on the job's mesh."""
+    res = job["mesh"].trace(job["orig"], job["dirs"], tmax=job.get("tmax"),
+                            start_face=job.get("start_face"), want_tets=True, want_steps=True)
+    return _host(res)
+
+
+def _same(a, b, what):
+    for k in KEYS:
+        x, y = a[k], b[k]
+        assert x.shape == y.shape, (what, k)
+        if x.dtype.kind == "f":
+            ok = (x == y) | (np.isnan(x) & np.isnan(y))
+        else:
+            ok = x == y
+        assert ok.all(), (what, k, int((~ok).sum()))
+
+
+def _fill(jobs):
+    for j in jobs:
+        j["out"]["tri"].fill_(-7)
+        j["out"]["t"].fill_(123.0)
+        j["out"]["bary"].fill_(5.0)
+        j["out"]["steps"].fill_(-9)
+
+
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_batch_matches_single(tetrt, scenes, uploaded, block):
+    jobs = _jobs(tetrt, scenes, uploaded)
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))
+    b.set(jobs, block=block)
+    _fill(jobs)
+    b.launch()
+    for k, j in enumerate(jobs):
+        _same(_host(j["out"]), _single(j), "job %d" % k)
+    b.free()
+
+
+def test_batch_oracle(tetrt, scenes, uploaded):
+    jobs = [j for j in _jobs(tetrt, scenes, uploaded, empty_at=()) if j["orig"].shape[0] > 0]
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))
+    b.set(jobs)
+    b.launch()
+    for s, j in zip(scenes, jobs):
+        got = _host(j["out"])
+        ref = s["oracle"].trace(s["o"], s["d"], tmax=s["tmax"], start_face=s["sf"])
+        rep = compare(s["mesh"].points, s["oracle"].tri_verts, s["o"], s["d"], ref, got,
+                      tmax=s["tmax"])
+        assert rep["ok"], (s["spec"]["n"], rep)
+    b.free()
+
+
+@pytest.mark.parametrize("chunk", [10, 13])
+def test_batch_binned(tetrt, scenes, uploaded, chunk):
+    jobs = _jobs(tetrt, scenes, uploaded)
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))
+    b.set(jobs, sort=2, sort_chunk_log2=chunk, sort_dirq=3)
+    _fill(jobs)
+    b.launch()
+    for k, j in enumerate(jobs):
+        _same(_host(j["out"]), _single(j), "binned job %d" % k)
+    b.free()
+
+
+def test_batch_graph_replays(tetrt, scenes, uploaded):
+    jobs = _jobs(tetrt, scenes, uploaded)
+    cap = sum(int(j["orig"].shape[0]) for j in jobs)
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=cap)
+    b.set(jobs, sort=2, sort_chunk_log2=10)
+    want = [_single(j) for j in jobs]
+    for rep in range(3):
+        _fill(jobs)
+        torch.cuda.synchronize()
+        x = torch.randn(1 << 20, device="cuda:0")
+        (x * 2.0).sum().item()          # unrelated eager work between replays
+        b.graph_launch()
+        for k, j in enumerate(jobs):
+            _same(_host(j["out"]), want[k], "replay %d job %d" % (rep, k))
+    # same shape, other rays: the captured graph reads the new table
+    jobs2 = _jobs(tetrt, scenes, uploaded, reverse=True)
+    b.set(jobs2, sort=2, sort_chunk_log2=10)
+    _fill(jobs2)
+    b.graph_launch()
+    for k, j in enumerate(jobs2):
+        _same(_host(j["out"]), _single(j), "new table job %d" % k)
+    # another shape: fewer jobs, binning off -> captured again
+    jobs3 = jobs2[:4]
+    b.set(jobs3, sort=1)
+    _fill(jobs3)
+    b.graph_launch()
+    for k, j in enumerate(jobs3):
+        _same(_host(j["out"]), _single(j), "new shape job %d" % k)
+    b.free()
+
+
+def test_batch_tune(tetrt, scenes, uploaded):
+    jobs = _jobs(tetrt, scenes, uploaded)
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))
+    b.set(jobs)
+    chosen, ms = b.tune(reps=2)
+    assert chosen["block"] in (64, 128, 256) and chosen["sort"] in (1, 2) and ms > 0
+    _fill(jobs)
+    b.launch()
+    for k, j in enumerate(jobs):
+        _same(_host(j["out"]), _single(j), "tuned job %d" % k)
+    b.free()
+
+
+def test_batch_errors(tetrt, scenes, uploaded):
+    s = scenes[0]
+    other = tetrt.upload(s["mesh"].points, s["mesh"].tets, s["mesh"].nbrs, s["mesh"].cflag,
+                         layout="tet32n")
+    jobs = _jobs(tetrt, scenes[:2], uploaded[:2], empty_at=())
+    n = sum(int(j["orig"].shape[0]) for j in jobs)
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=n)
+    mixed = list(jobs)
+    mixed[1] = dict(jobs[1], mesh=other)
+    with pytest.raises(tetrt.TetRTError, match="layout"):
+        b.set(mixed)
+    with pytest.raises(tetrt.TetRTError, match="precision"):
+        b.set(jobs, eps=1e-6)
+    with pytest.raises(tetrt.TetRTError, match="one lane per ray"):
+        b.set(jobs, kernel=2)
+    with pytest.raises(tetrt.TetRTError, match="n_jobs"):
+        b.set(jobs + jobs)
+    small = tetrt.Batch(max_jobs=len(jobs), max_rays=n - 1)
+    with pytest.raises(tetrt.TetRTError, match="max_rays"):
+        small.set(jobs)
+    # a failed set leaves the previous jobs in place
+    b.set(jobs)
+    with pytest.raises(tetrt.TetRTError, match="layout"):
+        b.set(mixed)
+    _fill(jobs)
+    b.launch()
+    for k, j in enumerate(jobs):
+        _same(_host(j["out"]), _single(j), "after errors job %d" % k)
+    small.free()
+    b.free()
+    other.free()

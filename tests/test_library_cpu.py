@@ -118,3 +118,36 @@ def test_sfc_key_argument_checks(tetrt):
         tetrt.tetrt_sfc_keys(np.array([[8, 0, 0]], np.uint32), bits=3)
     with pytest.raises(tetrt.TetRTError):
         tetrt.tetrt_sfc_keys(np.zeros((1, 3), np.uint32), bits=22)
+
+
+def test_batch_argument_errors(tetrt):
+    """tm_batch_* reject bad arguments before touching a device."""
+    lib = tetrt.binding._load()
+    h = C.c_void_p()
+    assert lib.tm_batch_create(0, 10, C.byref(h)) == -1 and "max_jobs" in tetrt.tm_last_error()
+    assert lib.tm_batch_create(70000, 10, C.byref(h)) == -1
+    assert lib.tm_batch_create(4, -1, C.byref(h)) == -1 and "max_rays" in tetrt.tm_last_error()
+    assert lib.tm_batch_create(4, 1 << 33, C.byref(h)) == -1
+    assert lib.tm_batch_create(4, 10, None) == -1
+    assert lib.tm_batch_set(None, 0, None, None, None) == -1 and "NULL batch" in tetrt.tm_last_error()
+    assert lib.tm_batch_launch(None, None) == -1
+    assert lib.tm_batch_graph_launch(None, None) == -1
+    assert lib.tm_batch_tune(None, 3, None, None, None) == -1
+    assert lib.tm_batch_free(None) == 0
+
+
+def test_server_argument_errors(tetrt):
+    """tm_server_* and tm_request_rays reject bad arguments before touching a device."""
+    lib = tetrt.binding._load()
+    h = C.c_void_p()
+    assert lib.tm_server_create(None, 1, None, C.byref(h)) == -1 and "meshes" in tetrt.tm_last_error()
+    assert lib.tm_server_create(None, 1, None, None) == -1
+    i = C.c_int64()
+    assert lib.tm_server_submit(None, None, C.byref(i)) == -1
+    assert lib.tm_server_step(None, None, None) == -1
+    n = C.c_int32()
+    assert lib.tm_server_poll(None, None, 0, C.byref(n)) == -1
+    assert lib.tm_server_drain(None, None) == -1
+    assert lib.tm_server_pending(None, None, None, None) == -1
+    assert lib.tm_request_rays(None, None, 0, None, None, None, None, None, None, None) == -1
+    assert lib.tm_server_free(None) == 0

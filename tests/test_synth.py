@@ -108,3 +108,23 @@ def test_paper_config_spheres():
     assert np.all((sp[:, 3] >= 0.03) & (sp[:, 3] <= 0.12))
     # the camera at (0.5, 0.5, 0.02) is outside every sphere
     assert np.all(np.linalg.norm(sp[:, :3] - [0.5, 0.5, 0.02], axis=1) > sp[:, 3])
+
+
+def test_batch_specs_ranges_and_seeding():
+    from synth.batch import batch_specs, camera_rays, ao_from_hits
+    a = batch_specs(count=64, seed=10)
+    b = batch_specs(count=64, seed=10)
+    assert [s["n"] for s in a] == [s["n"] for s in b]
+    ns = np.array([s["n"] for s in a])
+    rays = np.array([s["rays"] for s in a])
+    assert ns.min() >= 8 and ns.max() <= 96 and len(set(ns)) > 20
+    assert rays.min() >= 1000 and rays.max() <= 1_000_000
+    for s in a:
+        assert 1 <= len(s["spheres"]) <= 10
+        assert np.all((s["eye"] > 0.0) & (s["eye"] < 1.0))
+        assert abs(np.linalg.norm(s["forward"]) - 1.0) < 1e-12
+    o, d = camera_rays(a[0])
+    assert o.shape == ((a[0]["rays"] + 1) // 2, 3) and d.dtype == np.float32
+    # AO rays: nothing hit -> empty; otherwise count rays leaving from hit faces
+    z = ao_from_hits(None, None, o, d, np.full(len(o), -1, np.int32), np.zeros(len(o), np.float32), 10, 1)
+    assert all(len(x) == 0 for x in z)
