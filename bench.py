@@ -40,8 +40,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper", choices=["paper", "tiny", "batch64"],
-                    help="batch64: 64 uneven meshes in one batched launch (prints its own line)")
+    ap.add_argument("--workload", default="paper", choices=["paper", "tiny", "batch64", "serve", "ablate"],
+                    help="batch64: 64 uneven meshes in one batched launch; serve: Poisson request "
+                         "stream over 16 resident meshes; ablate: record layouts x curve orders and "
+                         "camera distances on the 12.6M-tet scene (each prints its own line)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="serve: seconds per offered rate")
+    ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9",
+                    help="serve: offered rates as fractions of the measured capacity")
+    ap.add_argument("--serve-big", type=int, default=1, help="serve: include the 12.6M-tet mesh")
     ap.add_argument("--batch-meshes", type=int, default=64, help="batch64: number of meshes")
     ap.add_argument("--tile", type=int, default=8, help="pixel tile edge for ray order (1 = row-major)")
     ap.add_argument("--sfc", default="hilbert", choices=["hilbert", "morton", "none"])
@@ -90,6 +96,10 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     if args.workload == "batch64":
         return bench_batch(args, tetrt, dev, log)
+    if args.workload == "serve":
+        return bench_serve(args, tetrt, dev, log)
+    if args.workload == "ablate":
+        return bench_ablate(args, tetrt, dev, log)
 
     t0 = time.time()
     m, eye, W, H = workload(args.workload)
@@ -332,6 +342,201 @@ def bench_batch(args, tetrt, dev, log):
     print(json.dumps(line), flush=True)
     if mism:
         raise SystemExit("batched results differ from separate launches in %d values" % mism)
+
+
+def bench_serve(args, tetrt, dev, log):
+    """Serving: 16 resident meshes (15 of the many-mesh sizes, plus the 12.6M-tet
+    scene with --serve-big 1); requests with a uniform interior camera, resolution
+    uniform over {64, 256, 512, 1024}^2 and kind primary/shadow/AO at 50/25/25%.
+    First the capacity (a burst of requests drained at once), then a Poisson
+    stream at each offered fraction of it: p50/p99 latency from arrival to the
+    step that sees the request's last launch complete, and the achieved Mrays/s."""
+    import numpy as np
+    import torch
+    from synth import config_mesh
+    from synth.batch import batch_specs, spec_mesh
+
+    t0 = time.time()
+    hosts = [spec_mesh(s) for s in batch_specs(count=15 if args.serve_big else 16, seed=50)]
+    if args.serve_big:
+        hosts.append(config_mesh("paper"))
+    meshes = []
+    for m in hosts:
+        meshes.append(tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=args.layout, sfc=args.sfc))
+    tets = sum(m.n_tets for m in hosts)
+    del hosts
+    log("serve: %d meshes, %d tets, uploaded in %.0f s" % (len(meshes), tets, time.time() - t0))
+    rng = np.random.default_rng(77)
+    sizes = [64, 256, 512, 1024]
+    kinds = ["primary", "primary", "shadow", "ao"]
+
+    def request():
+        f = rng.normal(size=3)
+        f /= np.linalg.norm(f)
+        up = (0.0, 1.0, 0.0) if abs(f[1]) < 0.9 else (1.0, 0.0, 0.0)
+        S = sizes[int(rng.integers(0, 4))]
+        return dict(mesh=int(rng.integers(0, len(meshes))), kind=kinds[int(rng.integers(0, 4))],
+                    width=S, height=S, eye=rng.uniform(0.05, 0.95, 3), forward=f, up=up,
+                    fov_h_deg=60.0, light=rng.uniform(0.05, 0.95, 3), ao_tmax=0.1,
+                    seed=int(rng.integers(0, 1 << 31)))
+
+    n_buf = 96
+    bufs = [tetrt.outputs(1024 * 1024, dev) for _ in range(n_buf)]
+
+    def view(b, n):
+        return {"tri": b["tri"][:n], "t": b["t"][:n], "bary": b["bary"][:n]}
+
+    srv = tetrt.Server(meshes, max_rays=32 << 20, block=args.block, sort=args.sort)
+
+    # capacity: a burst of requests, drained
+    burst = [request() for _ in range(64)]
+    for _ in range(2):
+        for k, r in enumerate(burst):
+            srv.submit(view(bufs[k % n_buf], r["width"] * r["height"]), **r)
+            if k % n_buf == n_buf - 1:
+                srv.drain()
+        srv.drain()
+        srv.poll(4096)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter()
+    for k, r in enumerate(burst):
+        srv.submit(view(bufs[k % n_buf], r["width"] * r["height"]), **r)
+        if k % n_buf == n_buf - 1:
+            srv.drain()
+    srv.drain()
+    torch.cuda.synchronize()
+    burst_s = time.perf_counter() - t_b
+    done = srv.poll(4096)
+    burst_rays = sum(d["rays"] for d in done)
+    cap_rps = len(burst) / burst_s
+    log("serve: capacity %.0f requests/s, %.1f Mrays/s (burst of %d)" % (cap_rps, burst_rays / burst_s / 1e6, len(burst)))
+
+    loads = []
+    for frac in [float(x) for x in args.serve_loads.split(",") if x]:
+        rate = frac * cap_rps
+        n_req = max(20, int(rate * args.serve_seconds))
+        gaps = rng.exponential(1.0 / rate, n_req)
+        reqs = [request() for _ in range(n_req)]
+        free = list(range(n_buf))
+        owner, arrival, lat = {}, {}, []
+        rays = 0
+        start = time.monotonic_ns()
+        due = start + np.cumsum(gaps * 1e9).astype(np.int64)
+        nxt = 0
+        delayed = 0
+        while len(lat) < n_req:
+            now = time.monotonic_ns()
+            while nxt < n_req and due[nxt] <= now and free:
+                r = reqs[nxt]
+                b = free.pop()
+                i = srv.submit(view(bufs[b], r["width"] * r["height"]), **r)
+                owner[i] = b
+                arrival[i] = int(due[nxt])
+                delayed += int(now - due[nxt] > 1_000_000)
+                nxt += 1
+            srv.step()
+            for d in srv.poll(4096):
+                lat.append((d["done_ns"] - arrival[d["id"]]) * 1e-6)
+                rays += d["rays"]
+                free.append(owner.pop(d["id"]))
+        wall = (time.monotonic_ns() - start) * 1e-9
+        lat = np.array(lat)
+        entry = {"offered_frac": frac, "offered_rps": round(rate, 1), "requests": n_req,
+                 "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                 "mrays_s": round(rays / wall / 1e6, 2), "late_submits": delayed}
+        log("serve: %s" % json.dumps(entry))
+        loads.append(entry)
+    srv.free()
+    for m in meshes:
+        m.free()
+    line = {
+        "metric": "serving p50/p99 latency over 16 resident meshes",
+        "value": loads[-1]["p99_ms"] if loads else None, "unit": "ms (p99 at the highest offered load)",
+        "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16 meshes (%d tets), Poisson requests: interior camera, "
+                               "64^2..1024^2, primary/shadow/AO 50/25/25%%" % tets,
+                   "layout": args.layout, "seconds_per_load": args.serve_seconds},
+        "capacity": {"requests_s": round(cap_rps, 1), "mrays_s": round(burst_rays / burst_s / 1e6, 2)},
+        "loads": loads,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_ablate(args, tetrt, dev, log):
+    """The paper's ablations on the 12.6M-tet scene: every record layout under
+    every curve order (time per pass, bytes per tet, the paper's Table 3, Table 4
+    and Fig. 8 analogues), then primary walks from cameras at growing depth
+    into the scene (visited tets per pixel and time, the Table 5 analogue).  The
+    AO rays are built once, from the first configuration's primary hits."""
+    import numpy as np
+    import torch
+    from synth import config_mesh, pinhole_rays, ao_rays, tri_geometry
+
+    m = config_mesh("paper")
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.02), 1920, 1080, 60.0, tile=args.tile)
+    po, pd = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+    K = args.steps
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    rows, ao_set = [], None
+    for layout in ("tet20", "tet16", "tet32n"):
+        for sfc in ("hilbert", "morton", "none"):
+            t0 = time.time()
+            mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=layout, sfc=sfc)
+            up_s = time.time() - t0
+            res = mesh.trace(po, pd, want_steps=True)
+            if ao_set is None:
+                tri = res["tri"].cpu().numpy()
+                tp = res["t"].cpu().numpy()
+                hit = tri >= 0
+                hp = o[hit].astype(np.float64) + tp[hit, None].astype(np.float64) * d[hit].astype(np.float64)
+                nrm, _ = tri_geometry(m.points, mesh.tri_vertices(tri[hit]))
+                ao, ad, atm, parent = ao_rays(hp, nrm, d[hit], k=args.ao, seed=3, tmax=0.1)
+                ao_set = [torch.from_numpy(x).to(dev) for x in (ao, ad, atm, tri[hit][parent].astype(np.int32))]
+            A = ao_set
+            out_p = tetrt.outputs(po.shape[0], dev)
+            out_a = tetrt.outputs(A[0].shape[0], dev)
+            ms_p = timed(lambda: mesh.trace_into(out_p, po, pd, block=args.block))
+            ms_a = timed(lambda: mesh.trace_into(out_a, A[0], A[1], tmax=A[2], start_face=A[3], block=args.block))
+            steps_p = float(res["steps"].double().mean().item())
+            row = {"layout": layout, "sfc": sfc, "primary_ms": round(ms_p, 4), "ao_ms": round(ms_a, 4),
+                   "mrays_s": round((po.shape[0] + A[0].shape[0]) / ((ms_p + ms_a) * 1e-3) / 1e6, 1),
+                   "hot_bytes_per_tet": round(mesh.info["hot_bytes"] / m.n_tets, 2),
+                   "all_bytes_per_tet": round((mesh.info["hot_bytes"] + mesh.info["cold_bytes"]) / m.n_tets, 2),
+                   "primary_mean_steps": round(steps_p, 2), "upload_s": round(up_s, 2)}
+            log("ablate: %s" % json.dumps(row))
+            rows.append(row)
+            mesh.free()
+    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=args.layout, sfc=args.sfc)
+    cams = []
+    for z in (0.02, 0.1, 0.2, 0.3, 0.4):
+        oc, dc, _ = pinhole_rays((0.5, 0.5, z), 1920, 1080, 60.0, tile=args.tile)
+        oc, dc = torch.from_numpy(oc).to(dev), torch.from_numpy(dc).to(dev)
+        res = mesh.trace(oc, dc, want_steps=True)
+        out = tetrt.outputs(oc.shape[0], dev)
+        ms = timed(lambda: mesh.trace_into(out, oc, dc, block=args.block))
+        st = res["steps"].double()
+        row = {"eye_z": z, "primary_ms": round(ms, 4), "mean_steps": round(float(st.mean().item()), 2),
+               "hit_rate": round(float((res["tri"] >= 0).double().mean().item()), 4),
+               "mrays_s": round(oc.shape[0] / (ms * 1e-3) / 1e6, 1)}
+        log("ablate: %s" % json.dumps(row))
+        cams.append(row)
+    mesh.free()
+    print(json.dumps({"metric": "ablations at 12.6M tets", "layouts_x_orders": rows, "camera_depth": cams,
+                      "config": {"workload": "kuhn128-jitter0.1-20spheres, 1920x1080 + %d AO/hit" % args.ao,
+                                 "steps": K, "block": args.block}}), flush=True)
 
 
 def cpu_baseline(m, o, d, ao, ad, atm, sf, parent, hit, stride, log):

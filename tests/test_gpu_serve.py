@@ -95,7 +95,7 @@ def test_secondary_rays_properties(tetrt, scene, kind):
     r1 = _host(_rays(tetrt, mesh, req, 1, dict(r0, tri=res0["tri"], t=res0["t"])))
     h0, c0 = _host(res0), _host(r0)
     hit = h0["tri"] >= 0
-    assert hit.mean() > 0.1
+    assert hit.sum() >= 500
     # origins: the hit points; start faces: the hit triangles; no hit -> zero direction
     hp = c0["orig"].astype(np.float64) + h0["t"][:, None].astype(np.float64) * c0["dirs"].astype(np.float64)
     assert np.abs(r1["orig"][hit] - hp[hit]).max() < 1e-6
@@ -115,8 +115,8 @@ def test_secondary_rays_properties(tetrt, scene, kind):
         n *= np.where(np.einsum("ij,ij->i", n, c0["dirs"][hit]) > 0, -1.0, 1.0)[:, None]
         cos = np.einsum("ij,ij->i", n, d)
         assert cos.min() > -1e-5
-        # cosine-weighted: E[cos] = 2/3
-        assert abs(cos.mean() - 2.0 / 3.0) < 0.02
+        # cosine-weighted: E[cos] = 2/3 (standard deviation of cos is sqrt(1/18))
+        assert abs(cos.mean() - 2.0 / 3.0) < 5.0 * np.sqrt(1.0 / 18.0 / hit.sum())
 
 
 @pytest.mark.parametrize("kind", ["primary", "shadow", "ao"])
