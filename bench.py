@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--sort-cells", type=int, default=0, help="log2 origin cells per axis (0 = default)")
     ap.add_argument("--eye", default="", help="camera position x,y,z (default: the workload's)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-stride", type=int, default=4,
+    ap.add_argument("--cpu-stride", type=int, default=2,
                     help="oracle sample: every n-th primary ray and the AO rays of its hits")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a device copy of this size (counter calibration runs)")
@@ -152,16 +152,31 @@ def main():
              "t": torch.empty(n_a, dtype=torch.float32, device=dev),
              "bary": torch.empty((n_a, 2), dtype=torch.float32, device=dev)}
 
-    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill, sort=args.sort,
-              sort_chunk_log2=args.sort_chunk, sort_dirq=args.sort_dirq,
-              sort_cells_log2=args.sort_cells)
+    # binning: the library's automatic rule (batches of at least 2^18 rays that carry
+    # tmax), run as its own kernel so that the walk kernel is timed apart
+    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill)
+    skw = dict(sort_chunk_log2=args.sort_chunk, sort_dirq=args.sort_dirq, sort_cells_log2=args.sort_cells)
+    bin_p = args.sort == 2
+    bin_a = args.sort == 2 or (args.sort == 0 and n_a >= (1 << 18))
+    ord_p = torch.empty(n_p, dtype=torch.int32, device=dev) if bin_p else None
+    ord_a = torch.empty(n_a, dtype=torch.int32, device=dev) if bin_a else None
 
-    def step():
-        mesh.trace_into(out_p, po, pd, **kw)
-        mesh.trace_into(out_a, ao_t, ad_t, tmax=atm_t, start_face=sf_t, **kw)
+    def launch(ev=None):
+        rec = (lambda k: ev[k].record()) if ev else (lambda k: None)
+        rec(0)
+        if bin_p:
+            mesh.bin_rays(po, pd, ord_p, **skw)
+        rec(1)
+        mesh.trace_into(out_p, po, pd, order=ord_p, sort=1, **kw)
+        rec(2)
+        if bin_a:
+            mesh.bin_rays(ao_t, ad_t, ord_a, **skw)
+        rec(3)
+        mesh.trace_into(out_a, ao_t, ad_t, tmax=atm_t, start_face=sf_t, order=ord_a, sort=1, **kw)
+        rec(4)
 
     for _ in range(args.warmup):
-        step()
+        launch()
     if args.copy_probe_mib > 0:
         nbytes = args.copy_probe_mib << 20
         src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -173,19 +188,15 @@ def main():
     torch.cuda.synchronize()
 
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
     t_wall = time.perf_counter()
     for k in range(K):
-        ev[k][0].record()
-        mesh.trace_into(out_p, po, pd, **kw)
-        ev[k][1].record()
-        mesh.trace_into(out_a, ao_t, ad_t, tmax=atm_t, start_face=sf_t, **kw)
-        ev[k][2].record()
+        launch(ev[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
-    ms_p = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)])
-    ms_a = np.array([ev[k][1].elapsed_time(ev[k][2]) for k in range(K)])
-    ms_step = float(ev[0][0].elapsed_time(ev[K - 1][2]) / K)
+    seg = lambda a, b: np.array([ev[k][a].elapsed_time(ev[k][b]) for k in range(K)])
+    ms_bin_p, ms_p, ms_bin_a, ms_a = seg(0, 1), seg(1, 2), seg(2, 3), seg(3, 4)
+    ms_step = float(ev[0][0].elapsed_time(ev[K - 1][4]) / K)
     rays = n_p + n_a
     value = rays / (ms_step * 1e-3) / 1e6
 
@@ -218,7 +229,7 @@ def main():
             ("row-major" if args.tile <= 1 else "%dx%d tiles" % (args.tile, args.tile)),
             "layout": args.layout, "sfc": args.sfc, "block": args.block,
             "kernel": {0: "auto", 1: "one lane per ray", 2: "persistent lanes"}[args.kernel],
-            "ray_binning": {0: "auto", 1: "off", 2: "on"}[args.sort], "eye": list(eye),
+            "ray_binning": {0: "auto (AO rays)", 1: "off", 2: "on"}[args.sort], "eye": list(eye),
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -228,6 +239,8 @@ def main():
         },
         "detail": {
             "primary_ms": round(float(ms_p.mean()), 4), "ao_ms": round(float(ms_a.mean()), 4),
+            "primary_binning_ms": round(float(ms_bin_p.mean()), 4) if bin_p else None,
+            "ao_binning_ms": round(float(ms_bin_a.mean()), 4) if bin_a else None,
             "primary_mrays_s": round(n_p / ms_p.mean() / 1e3, 2),
             "ao_mrays_s": round(n_a / ms_a.mean() / 1e3, 2),
             "primary_mean_steps": round(float(steps_p.mean()), 2),

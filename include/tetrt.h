@@ -114,7 +114,7 @@ typedef struct {
                             direction, then by the low bits of the Morton index of their
                             origin's cell, and traced in that order; the outputs stay at
                             the caller's positions */
-    int32_t sort_chunk_log2; /* rays per chunk = 2^this, 10..13 (0 = 12) */
+    int32_t sort_chunk_log2; /* rays per chunk = 2^this, 10..13 (0 = 11) */
     int32_t sort_cells_log2; /* origin cells per axis = 2^this, 1..7 (0 = 5) */
     int32_t sort_dirq;   /* direction bins per axis, 1..4 (0 = 4) */
     float eps;           /* precision variant, 0 = off.  When > 0 (one lane per ray only), a
@@ -129,6 +129,10 @@ typedef struct {
     int64_t workspace_bytes; /* size of workspace (tetmesh_trace_workspace gives the need) */
     int32_t* fp64_steps; /* device int32 [n_rays] or NULL: out: walk steps decided in float64
                             (0 when eps = 0) */
+    const int32_t* order; /* device int32 [n_rays] or NULL: trace the rays in this order (lane j
+                            takes ray order[j]; a permutation of 0..n_rays-1, e.g. from
+                            tetmesh_bin_rays; entries out of range are skipped).  Replaces
+                            the call's own binning (sort is then ignored) */
 } tm_trace_opts;
 
 /*
@@ -222,6 +226,15 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
  */
 int tetmesh_locate(tm_mesh m, int64_t n, const float* d_pts, int32_t* d_tet, void* hip_stream);
 
+/* tetmesh_bin_rays -- the ray order trace_closest's binning would use (the
+ * sort option's chunked grouping by direction and origin cell, with
+ * sort_chunk_log2, sort_cells_log2 and sort_dirq of opts), written to d_order
+ * (device int32 [n_rays], caller-owned) for a later trace_closest with
+ * opts->order.  Lets a caller bin once and trace several times, or time the
+ * two kernels apart.  0 <= n_rays < 2^31.  Errors: TM_ERR_ARG, TM_ERR_HIP. */
+int tetmesh_bin_rays(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d_dir,
+                     const tm_trace_opts* opts, int32_t* d_order, void* hip_stream);
+
 /* tetmesh_trace_workspace -- bytes of device workspace a trace_closest call with
  * these arguments needs (0 when it bins no rays).  d_tmax_present: the d_tmax
  * argument of that call (only tested for NULL).  *bytes host out. */
@@ -266,7 +279,7 @@ int tm_batch_create(int32_t max_jobs, int64_t max_rays, tm_batch* out);
 
 /* tm_batch_set -- replace the batch's jobs.  jobs host [n_jobs] (0 <= n_jobs <=
  * max_jobs), copied.  opts as for trace_closest, except: kernel 0 or 1, eps = 0,
- * xcds, refill, grid_cap, workspace and fp64_steps are ignored, and the binning
+ * xcds, refill, grid_cap, workspace, fp64_steps and order are ignored, and the binning
  * chunk size is one for all jobs (sort = 0 bins the jobs that carry tmax and
  * have at least 2^18 rays).  The new table is copied to the device on
  * hip_stream, after the batch's previous table copy has left the staging

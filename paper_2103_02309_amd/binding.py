@@ -34,7 +34,7 @@ class _TraceOpts(C.Structure):
                 ("refill", C.c_int32), ("grid_cap", C.c_int32), ("xcds", C.c_int32),
                 ("sort", C.c_int32), ("sort_chunk_log2", C.c_int32), ("sort_cells_log2", C.c_int32),
                 ("sort_dirq", C.c_int32), ("eps", C.c_float), ("workspace", C.c_void_p), ("workspace_bytes", C.c_int64),
-                ("fp64_steps", C.c_void_p)]
+                ("fp64_steps", C.c_void_p), ("order", C.c_void_p)]
 
 _TRACE_KEYS = ("max_steps", "block", "kernel", "refill", "grid_cap", "xcds", "sort",
                "sort_chunk_log2", "sort_cells_log2", "sort_dirq")
@@ -47,6 +47,9 @@ def _trace_opts(kw, workspace=None, fp64_steps=None, n=0):
     o.eps = float(kw.pop("eps", 0.0))
     if fp64_steps is not None:
         o.fp64_steps = _dev(fp64_steps, torch.int32, n, (), "fp64_steps")
+    order = kw.pop("order", None)
+    if order is not None:
+        o.order = _dev(order, torch.int32, n, (), "order")
     if kw:
         raise TypeError("unknown trace options: %s" % ", ".join(sorted(kw)))
     if workspace is not None:
@@ -117,6 +120,8 @@ def _load():
                                 C.POINTER(_TraceOpts), vp]
     L.tetmesh_trace_workspace.restype = C.c_int
     L.tetmesh_trace_workspace.argtypes = [vp, i64, vp, C.POINTER(_TraceOpts), C.POINTER(i64)]
+    L.tetmesh_bin_rays.restype = C.c_int
+    L.tetmesh_bin_rays.argtypes = [vp, i64, vp, vp, C.POINTER(_TraceOpts), vp, vp]
     L.tetmesh_locate.restype = C.c_int
     L.tetmesh_locate.argtypes = [vp, i64, vp, vp, vp]
     L.tetmesh_tri_vertices.restype = C.c_int
@@ -242,6 +247,15 @@ def tetmesh_trace_workspace(handle, n_rays, has_tmax, **opts):
                                            C.c_void_p(1 if has_tmax else 0), C.byref(o),
                                            C.byref(b)))
     return b.value
+
+
+def tetmesh_bin_rays(handle, orig, dirs, order, stream=None, **opts):
+    """Write the binning order of ``orig``/``dirs`` into ``order`` (int32 [n], device)."""
+    n = int(orig.shape[0])
+    o = _trace_opts(dict(opts))
+    _check(_load().tetmesh_bin_rays(C.c_void_p(handle), n, _dev(orig, torch.float32, n, (3,), "orig"),
+                                    _dev(dirs, torch.float32, n, (3,), "dirs"), C.byref(o),
+                                    _dev(order, torch.int32, n, (), "order"), _stream(stream)))
 
 
 def tetmesh_locate(handle, pts, out, stream=None):
@@ -457,6 +471,13 @@ class Mesh:
                       steps=out.get("steps"), workspace=workspace,
                       fp64_steps=out.get("fp64_steps"), stream=stream, **opts)
         return out
+
+    def bin_rays(self, orig, dirs, order=None, stream=None, **opts):
+        """The binning order of the rays (int32 [n] device tensor), for trace(order=...)."""
+        if order is None:
+            order = torch.empty(int(orig.shape[0]), dtype=torch.int32, device=orig.device)
+        tetmesh_bin_rays(self.handle, orig, dirs, order, stream, **opts)
+        return order
 
     def workspace_bytes(self, n_rays, has_tmax, **opts):
         return tetmesh_trace_workspace(self.handle, n_rays, has_tmax, **opts)

@@ -44,7 +44,7 @@ int sort_config(const tm_mesh_s* m, const tm_trace_opts& o, int64_t n, bool has_
                 tetrt::SortCfg* c, bool* on) {
     // automatic: bin batches of secondary-style rays (with tmax) of at least 2^18 rays
     *on = o.sort == 2 || (o.sort == 0 && has_tmax && n >= (int64_t(1) << 18));
-    c->chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 12;
+    c->chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 11;
     c->cells_log2 = o.sort_cells_log2 ? o.sort_cells_log2 : 5;
     c->dirq = o.sort_dirq ? o.sort_dirq : 4;
     if (c->chunk_log2 < 10 || c->chunk_log2 > 13 || c->cells_log2 < 1 || c->cells_log2 > 7 ||
@@ -228,8 +228,9 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     bool binned = false;
     int rc = sort_config(m, o, n_rays, d_tmax != nullptr, &sc, &binned);
     if (rc != TM_OK) return rc;
+    if (o.order) binned = false;   // the caller's order replaces the call's binning
     tetrt::RayArgs r;
-    r.perm = nullptr;
+    r.perm = o.order;
     r.orig = d_orig;
     r.dir = d_dir;
     r.tmax = d_tmax;
@@ -298,6 +299,29 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     }
     e = tetrt::launch_trace(m->dev, r, c, stream);
     if (e != hipSuccess) return hip_fail(e, "trace_closest: kernel launch");
+    return TM_OK;
+}
+
+int tetmesh_bin_rays(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d_dir,
+                     const tm_trace_opts* opts, int32_t* d_order, void* hip_stream) {
+    tetrt::clear_error();
+    if (!m) return fail(TM_ERR_ARG, "tetmesh_bin_rays: NULL mesh");
+    if (n_rays < 0 || n_rays > int64_t(0x7FFFFFFF))
+        return fail(TM_ERR_ARG, "tetmesh_bin_rays: n_rays = %lld out of range [0, 2^31)", (long long)n_rays);
+    if (n_rays == 0) return TM_OK;
+    if (!d_orig || !d_dir || !d_order) return fail(TM_ERR_ARG, "tetmesh_bin_rays: NULL array");
+    tm_trace_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    o.sort = 2;
+    tetrt::SortCfg sc;
+    bool on = false;
+    int rc = sort_config(m, o, n_rays, true, &sc, &on);
+    if (rc != TM_OK) return rc;
+    int32_t* perm = nullptr;
+    hipError_t e = tetrt::launch_sort(sc, d_orig, d_dir, n_rays, d_order, &perm,
+                                      static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "tetmesh_bin_rays: kernel launch");
     return TM_OK;
 }
 

@@ -84,7 +84,7 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
     if (o.eps != 0.0f) return fail(TM_ERR_ARG, "tm_batch_set: the precision variant (eps > 0) is not batched");
     if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "tm_batch_set: sort must be 0, 1 or 2");
     const int32_t block = o.block ? o.block : 256;
-    const int32_t chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 12;
+    const int32_t chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 11;
     table->assign(size_t(n_jobs), tetrt::Job{});
     int64_t blocks = 0, chunks = 0, rays = 0, perm_at = 0;
     int32_t layout = -1;

@@ -290,6 +290,29 @@ __device__ __forceinline__ void make_ccw(Walk& w) {
     w.e1 = sw ? e2 : e1; w.e2 = sw ? e1 : e2;
 }
 
+// make_ccw with the orientation decided in float64 (precision variant): the
+// three face vertices A, B, C (in slot order) are projected in float64 about
+// the origin X.  A face that contains the ray's 2-D origin on or near one of
+// its edges -- a ray along a mesh edge starts on two such faces -- has a
+// float32 orientation of random sign, and a wrongly oriented face misleads
+// every later exit decision.
+__device__ __forceinline__ void make_ccw64(const Frame& f, float Xx, float Xy, float Xz, float4 A,
+                                           float4 B, float4 C, Walk& w) {
+    const double pox = fma(double(f.ux), double(Xx), fma(double(f.uy), double(Xy), double(f.uz) * double(Xz)));
+    const double poy = fma(double(f.vx), double(Xx), fma(double(f.vy), double(Xy), double(f.vz) * double(Xz)));
+    double x0, y0, x1, y1, x2, y2;
+    project64(f, pox, poy, A, x0, y0);
+    project64(f, pox, poy, B, x1, y1);
+    project64(f, pox, poy, C, x2, y2);
+    const bool sw = det2d(x1 - x0, y1 - y0, x2 - x0, y2 - y0) < 0.0;
+    const int32_t a1 = w.a1, a2 = w.a2;
+    const float q1x = w.q1x, q1y = w.q1y, q2x = w.q2x, q2y = w.q2y, e1 = w.e1, e2 = w.e2;
+    w.a1 = sw ? a2 : a1; w.a2 = sw ? a1 : a2;
+    w.q1x = sw ? q2x : q1x; w.q2x = sw ? q1x : q2x;
+    w.q1y = sw ? q2y : q1y; w.q2y = sw ? q1y : q2y;
+    w.e1 = sw ? e2 : e1; w.e2 = sw ? e1 : e2;
+}
+
 // One step of the walk (Algorithm 1 with Algorithms 4-5 or 6-7), branch-free
 // (apart from the rare float64 re-evaluation of the precision variant).
 template <bool DEPTH, int LAYOUT, bool PREC>
@@ -393,7 +416,10 @@ __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const
                               : next_field<kTet20>(R, r, 0u, 0);
     if (LAYOUT == kTet32N) w.vxn = int32_t(pick4(R.w0, R.w1, R.w2, R.w3, r));
     w.cur = tet;
-    make_ccw(w);
+    if (std::is_same<T, double>::value)
+        make_ccw64(f, Xx, Xy, Xz, PA, PB, PC, w);
+    else
+        make_ccw(w);
     return float(best);
 }
 
@@ -470,6 +496,71 @@ __device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float 
     return TM_RAY_STEP_CAP;
 }
 
+// Precision variant: make sure the start tet contains the point, with
+// orientations in float64.  The straight-line location decides its last
+// crossing in float32, so a point within rounding distance of a face, edge or
+// vertex (a ray that starts on a mesh edge) can land in a neighbour of the tet
+// that holds it; a walk started in a tet that does not contain its origin
+// breaks the invariant that the entry face surrounds the ray.  While the point
+// is on the outer side of a face, step across that face (at most 16 times).
+// v receives the ascending vertex ids of the returned tet.
+template <int LAYOUT>
+__device__ int32_t contain64(const DevMesh& m, const Mem& M, int32_t tet, int32_t v[4], float px,
+                             float py, float pz) {
+    for (int it = 0; it < 16; ++it) {
+        const int4 sv = reinterpret_cast<const int4*>(m.tetv)[tet];
+        v[0] = sv.x; v[1] = sv.y; v[2] = sv.z; v[3] = sv.w;
+        double X[4], Y[4], Z[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float4 P = load_pt(M, uint32_t(v[k]));
+            X[k] = double(P.x) - double(px);
+            Y[k] = double(P.y) - double(py);
+            Z[k] = double(P.z) - double(pz);
+        }
+        // orientation of the tet, and of each face with the point in place of its
+        // opposite vertex (the point is the origin of these coordinates)
+        const double e1x = X[1] - X[0], e1y = Y[1] - Y[0], e1z = Z[1] - Z[0];
+        const double e2x = X[2] - X[0], e2y = Y[2] - Y[0], e2z = Z[2] - Z[0];
+        const double e3x = X[3] - X[0], e3y = Y[3] - Y[0], e3z = Z[3] - Z[0];
+        const double vol = e1x * (e2y * e3z - e2z * e3y) - e1y * (e2x * e3z - e2z * e3x) +
+                           e1z * (e2x * e3y - e2y * e3x);
+        int out = -1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int A = j == 0 ? 1 : 0;
+            const int B = j <= 1 ? 2 : 1;
+            const int C = j <= 2 ? 3 : 2;
+            // triple product of the face vertices seen from the point, signed as the
+            // tet's volume with the point replacing vertex j
+            double t = X[A] * (Y[B] * Z[C] - Z[B] * Y[C]) - Y[A] * (X[B] * Z[C] - Z[B] * X[C]) +
+                       Z[A] * (X[B] * Y[C] - Y[B] * X[C]);
+            if (j == 1 || j == 3) t = -t;   // odd permutations of (0, 1, 2, 3)
+            if (out < 0 && t * vol < 0.0) out = j;
+        }
+        if (out < 0) return tet;
+        const Rec R = load_rec<LAYOUT>(M, uint32_t(tet));
+        const uint32_t field = LAYOUT == kTet16 ? next_field<kTet16>(R, out, uint32_t(m.n3[tet]), 3)
+                                                : pick4(R.n0, R.n1, R.n2, R.n3, out);
+        int32_t nt;
+        if (field == kBoundary) return tet;
+        if (field & 0x80000000u) {
+            const uint32_t cf = field & kIdMask;
+            if (cf >= uint32_t(m.ntri)) return tet;
+            const int4 pr = reinterpret_cast<const int4*>(m.cft)[cf];
+            nt = pr.x == tet ? pr.y : pr.x;
+            if (nt < 0) return tet;
+        } else {
+            nt = int32_t(field);
+        }
+        if (uint32_t(nt) >= uint32_t(m.nt)) return tet;
+        tet = nt;
+    }
+    const int4 sv = reinterpret_cast<const int4*>(m.tetv)[tet];
+    v[0] = sv.x; v[1] = sv.y; v[2] = sv.z; v[3] = sv.w;
+    return tet;
+}
+
 // Everything a lane keeps for one ray between set-up and the result.
 struct Ray {
     Frame f;
@@ -538,7 +629,10 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
         project(s.f, PB, s.w.q1x, s.w.q1y);
         project(s.f, PC, s.w.q2x, s.w.q2y);
         if (TMAX) { s.w.e0 = depth(s.g, PA); s.w.e1 = depth(s.g, PB); s.w.e2 = depth(s.g, PC); }
-        make_ccw(s.w);
+        if (PREC)
+            make_ccw64(s.f, ox, oy, oz, PA, PB, PC, s.w);
+        else
+            make_ccw(s.w);
         s.w.next = uint32_t(start);
         s.w.cur = int32_t(0x80000000u | uint32_t(sf));   // the start tet's field for this face
         return true;
@@ -555,6 +649,7 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
         tet = locate_point<LAYOUT, PREC>(m, M, ox, oy, oz, r.max_steps, eps, v);
         if (tet < 0) { write_code(r, i, tet, 0); return false; }
     }
+    if (PREC) tet = contain64<LAYOUT>(m, M, tet, v, ox, oy, oz);
     specialized_basis(dx, dy, dz, s.f);
     set_origin(s.f, ox, oy, oz);
     if (TMAX) set_depth(s.g, dx, dy, dz, ox, oy, oz);
@@ -637,6 +732,7 @@ k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds)) * blockDim.x + threadIdx.x;
     if (j >= r.n) return;
     const int64_t i = r.perm ? int64_t(r.perm[j]) : j;
+    if (uint64_t(i) >= uint64_t(r.n)) return;   // a caller's order that is no permutation
     const Mem M = make_mem<LAYOUT>(m);
     Ray s;
     if (!setup_ray<TMAX, LAYOUT, PREC>(m, M, r, i, s, kn.eps)) return;
@@ -678,7 +774,10 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
         if (!has) {
             while (j < r.n) {
                 i = r.perm ? int64_t(r.perm[j]) : j;
-                if (setup_ray<TMAX, LAYOUT, false>(m, M, r, i, s, 0.0f)) { has = true; break; }
+                if (uint64_t(i) < uint64_t(r.n) && setup_ray<TMAX, LAYOUT, false>(m, M, r, i, s, 0.0f)) {
+                    has = true;
+                    break;
+                }
                 j += L;
             }
         }
@@ -713,6 +812,7 @@ k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs) {
     const int64_t j = (b - jobs[lo].block0) * blockDim.x + threadIdx.x;
     if (j >= r.n) return;
     const int64_t i = r.perm ? int64_t(r.perm[j]) : j;
+    if (uint64_t(i) >= uint64_t(r.n)) return;
     const Mem M = make_mem<LAYOUT>(m);
     Ray s;
     if (!setup_ray<true, LAYOUT, false>(m, M, r, i, s, 0.0f)) return;
