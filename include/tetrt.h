@@ -105,18 +105,23 @@ typedef struct {
                             refill, 1..64 (0 = 16) */
     int32_t grid_cap;    /* persistent lanes: at most this many blocks (0 = enough blocks
                             to fill every compute unit) */
-    int32_t xcds;        /* one lane per ray: number of accelerator dies (XCDs) that get one
-                            contiguous range of blocks each; 0 or 1 = off (round-robin
-                            placement, which balances the dies) */
+    int32_t xcds;        /* one lane per ray: number of accelerator dies (XCDs, 8 on MI355X)
+                            the blocks are renumbered for, so that consecutive blocks run
+                            on one die and share its L2.  0 = automatic: the device's dies
+                            for binned launches (or with order), off otherwise; 1 = off
+                            (the dispatcher's round-robin placement) */
     int32_t sort;        /* ray binning before the walk: 0 = automatic (on for batches of at
                             least 2^18 rays that carry tmax), 1 = off, 2 = on.  Inside each
                             chunk of consecutive rays, rays are grouped by quantised
                             direction, then by the low bits of the Morton index of their
                             origin's cell, and traced in that order; the outputs stay at
                             the caller's positions */
-    int32_t sort_chunk_log2; /* rays per chunk = 2^this, 10..13 (0 = 11) */
+    int32_t sort_chunk_log2; /* rays per chunk = 2^this, 10..13 (0 = 12) */
     int32_t sort_cells_log2; /* origin cells per axis = 2^this, 1..7 (0 = 5) */
     int32_t sort_dirq;   /* direction bins per axis, 1..4 (0 = 4) */
+    int32_t xcd_blocks;  /* with xcds > 1: consecutive blocks per die (0 = one contiguous
+                            range of the launch per die; > 0 = runs of this many blocks,
+                            interleaved over the dies as they are dispatched) */
     float eps;           /* precision variant, 0 = off.  When > 0 (one lane per ray only), a
                             walk step whose float32 exit-face determinants det(q3, q_i) are
                             within eps * (|q3|_1 + |q_i|_1) of zero recomputes the projections
@@ -279,7 +284,7 @@ int tm_batch_create(int32_t max_jobs, int64_t max_rays, tm_batch* out);
 
 /* tm_batch_set -- replace the batch's jobs.  jobs host [n_jobs] (0 <= n_jobs <=
  * max_jobs), copied.  opts as for trace_closest, except: kernel 0 or 1, eps = 0,
- * xcds, refill, grid_cap, workspace, fp64_steps and order are ignored, and the binning
+ * xcd_blocks, refill, grid_cap, workspace, fp64_steps and order are ignored, and the binning
  * chunk size is one for all jobs (sort = 0 bins the jobs that carry tmax and
  * have at least 2^18 rays).  The new table is copied to the device on
  * hip_stream, after the batch's previous table copy has left the staging
@@ -303,9 +308,10 @@ int tm_batch_launch(tm_batch b, void* hip_stream);
 int tm_batch_graph_launch(tm_batch b, void* hip_stream);
 
 /* tm_batch_tune -- autotuner: times tm_batch_launch on the current jobs for
- * each block size (64, 128, 256) and binning setting (off; on with 2^11, 2^12,
- * 2^13 rays per chunk), reps timed launches each after one warm-up, with HIP
- * events on hip_stream, and keeps the fastest.  Overwrites the jobs' outputs
+ * each block size (64, 128, 256), binning setting (off; on with 2^11, 2^12,
+ * 2^13 rays per chunk) and die placement (round-robin; one contiguous range of
+ * blocks per XCD), reps timed launches each after one warm-up, with HIP events
+ * on hip_stream, and keeps the fastest.  Overwrites the jobs' outputs
  * (with the same results).  Synchronous.  chosen host, nullable: receives the
  * options kept; ms host, nullable: their mean launch time in milliseconds.
  * Errors: TM_ERR_ARG, TM_ERR_HIP. */

@@ -33,11 +33,11 @@ class _TraceOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("block", C.c_int32), ("kernel", C.c_int32),
                 ("refill", C.c_int32), ("grid_cap", C.c_int32), ("xcds", C.c_int32),
                 ("sort", C.c_int32), ("sort_chunk_log2", C.c_int32), ("sort_cells_log2", C.c_int32),
-                ("sort_dirq", C.c_int32), ("eps", C.c_float), ("workspace", C.c_void_p), ("workspace_bytes", C.c_int64),
+                ("sort_dirq", C.c_int32), ("xcd_blocks", C.c_int32), ("eps", C.c_float), ("workspace", C.c_void_p), ("workspace_bytes", C.c_int64),
                 ("fp64_steps", C.c_void_p), ("order", C.c_void_p)]
 
 _TRACE_KEYS = ("max_steps", "block", "kernel", "refill", "grid_cap", "xcds", "sort",
-               "sort_chunk_log2", "sort_cells_log2", "sort_dirq")
+               "sort_chunk_log2", "sort_cells_log2", "sort_dirq", "xcd_blocks")
 
 
 def _trace_opts(kw, workspace=None, fp64_steps=None, n=0):
@@ -226,7 +226,7 @@ def trace_closest(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, s
     """Enqueue a trace of ``orig``/``dirs`` ([n, 3] float32, device) writing into the
     given device tensors; asynchronous on ``stream`` (default: the current one).
     ``opts``: the tm_trace_opts fields (max_steps, block, kernel, refill, grid_cap,
-    xcds, sort, sort_chunk_log2, sort_cells_log2, sort_dirq, eps)."""
+    xcds, xcd_blocks, sort, sort_chunk_log2, sort_cells_log2, sort_dirq, eps, order)."""
     n = int(orig.shape[0]) if orig.dim() >= 1 else 0
     args = [_dev(orig, torch.float32, n, (3,), "orig"), _dev(dirs, torch.float32, n, (3,), "dirs"),
             _dev(tmax, torch.float32, n, (), "tmax", True),
@@ -336,7 +336,7 @@ def tm_batch_tune(batch, reps=5, stream=None):
     ms = C.c_float()
     _check(_load().tm_batch_tune(C.c_void_p(batch), int(reps), _stream(stream), C.byref(o),
                                  C.byref(ms)))
-    return {k: getattr(o, k) for k in ("block", "sort", "sort_chunk_log2")}, ms.value
+    return {k: getattr(o, k) for k in ("block", "sort", "sort_chunk_log2", "xcds")}, ms.value
 
 
 def tm_batch_free(batch):

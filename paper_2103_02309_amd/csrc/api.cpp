@@ -44,7 +44,7 @@ int sort_config(const tm_mesh_s* m, const tm_trace_opts& o, int64_t n, bool has_
                 tetrt::SortCfg* c, bool* on) {
     // automatic: bin batches of secondary-style rays (with tmax) of at least 2^18 rays
     *on = o.sort == 2 || (o.sort == 0 && has_tmax && n >= (int64_t(1) << 18));
-    c->chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 11;
+    c->chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 12;
     c->cells_log2 = o.sort_cells_log2 ? o.sort_cells_log2 : 5;
     c->dirq = o.sort_dirq ? o.sort_dirq : 4;
     if (c->chunk_log2 < 10 || c->chunk_log2 > 13 || c->cells_log2 < 1 || c->cells_log2 > 7 ||
@@ -217,6 +217,8 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     if (o.refill < 0 || o.refill > 64) return fail(TM_ERR_ARG, "trace_closest: refill must be in [0, 64]");
     if (o.grid_cap < 0) return fail(TM_ERR_ARG, "trace_closest: negative grid_cap");
     if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "trace_closest: xcds must be in [0, 64]");
+    if (o.xcd_blocks < 0 || o.xcd_blocks > 65536)
+        return fail(TM_ERR_ARG, "trace_closest: xcd_blocks must be in [0, 65536]");
     if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "trace_closest: sort must be 0, 1 or 2");
     if (!(o.eps >= 0.0f) || !(o.eps < 1.0f))
         return fail(TM_ERR_ARG, "trace_closest: eps must be in [0, 1)");
@@ -250,10 +252,12 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     c.waves_per_simd = 8;
     c.refill = o.refill ? o.refill : 16;
     c.grid_cap = o.grid_cap;
-    // MI355X: 256 CUs in 8 XCDs of 32
-    // off by default: round-robin placement balances the XCDs, and walk lengths vary
-    // across an image, so contiguous ranges leave some XCDs idle at the end
-    c.xcds = o.xcds ? o.xcds : 1;
+    // automatic: binned launches (their rays are ordered along the image, then by
+    // direction inside each chunk) give each XCD one contiguous range of blocks, so
+    // an XCD's L2 holds the tets of its part of the scene; unbinned launches keep
+    // the dispatcher's round-robin placement, which balances walks of uneven length
+    c.xcds = o.xcds ? o.xcds : ((binned || o.order) ? tetrt::xcd_count(m->cus) : 1);
+    c.xcd_blocks = o.xcd_blocks;
     // persistent lanes pay off once every lane gets several rays
     const int64_t lanes = int64_t(c.cus) * 4 * 64 * c.waves_per_simd;
     (void)lanes;

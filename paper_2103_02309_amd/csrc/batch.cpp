@@ -23,11 +23,11 @@ constexpr int64_t kPermAlign = 64;  // ints; each binned job's permutation start
 
 // The launch as captured in a graph; a new capture is needed when any differs.
 struct Shape {
-    int32_t n_jobs = -1, block = 0, chunk_log2 = 0, layout = -1;
+    int32_t n_jobs = -1, block = 0, chunk_log2 = 0, layout = -1, xcds = 1;
     int64_t blocks = -1, chunks = -1;
     bool operator==(const Shape& o) const {
         return n_jobs == o.n_jobs && block == o.block && chunk_log2 == o.chunk_log2 && layout == o.layout &&
-               blocks == o.blocks && chunks == o.chunks;
+               xcds == o.xcds && blocks == o.blocks && chunks == o.chunks;
     }
 };
 
@@ -35,6 +35,7 @@ struct Shape {
 
 struct tm_batch_s {
     int device = 0;
+    int cus = 256;
     int32_t max_jobs = 0;
     int64_t max_rays = 0;
     tetrt::Job* d_table = nullptr;
@@ -83,8 +84,9 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
         return fail(TM_ERR_ARG, "tm_batch_set: batches run one lane per ray (kernel 0 or 1)");
     if (o.eps != 0.0f) return fail(TM_ERR_ARG, "tm_batch_set: the precision variant (eps > 0) is not batched");
     if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "tm_batch_set: sort must be 0, 1 or 2");
+    if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "tm_batch_set: xcds must be in [0, 64]");
     const int32_t block = o.block ? o.block : 256;
-    const int32_t chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 11;
+    const int32_t chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 12;
     table->assign(size_t(n_jobs), tetrt::Job{});
     int64_t blocks = 0, chunks = 0, rays = 0, perm_at = 0;
     int32_t layout = -1;
@@ -144,6 +146,8 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
     shape->layout = layout < 0 ? 0 : layout;
     shape->blocks = blocks;
     shape->chunks = chunks;
+    // automatic as in trace_closest: one contiguous range per XCD when rays are binned
+    shape->xcds = o.xcds ? o.xcds : (chunks > 0 ? tetrt::xcd_count(b->cus) : 1);
     return TM_OK;
 }
 
@@ -178,7 +182,7 @@ hipError_t enqueue(const tm_batch_s* b, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (sh.chunks > 0) e = tetrt::launch_sort_batch(b->d_table, sh.n_jobs, sh.chunks, sh.chunk_log2, s);
     if (e != hipSuccess) return e;
-    return tetrt::launch_trace_batch(b->d_table, sh.n_jobs, sh.blocks, sh.block, sh.layout, s);
+    return tetrt::launch_trace_batch(b->d_table, sh.n_jobs, sh.blocks, sh.block, sh.layout, sh.xcds, s);
 }
 
 int check_batch(const tm_batch_s* b, const char* what) {
@@ -206,6 +210,11 @@ int tm_batch_create(int32_t max_jobs, int64_t max_rays, tm_batch* out) {
     tm_batch_s* b = new (std::nothrow) tm_batch_s();
     if (!b) return fail(TM_ERR_OOM, "tm_batch_create: host allocation failed");
     (void)hipGetDevice(&b->device);
+    if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess ||
+        b->cus <= 0) {
+        (void)hipGetLastError();
+        b->cus = 256;
+    }
     b->max_jobs = max_jobs;
     b->max_rays = max_rays;
     const size_t table_bytes = size_t(max_jobs) * sizeof(tetrt::Job);
@@ -298,15 +307,19 @@ int tm_batch_tune(tm_batch b, int32_t reps, void* hip_stream, tm_trace_opts* cho
     }
     static const int32_t kBlocks[3] = {64, 128, 256};
     static const int32_t kChunks[4] = {0, 11, 12, 13};  // 0 = no binning
+    const int32_t xcd_opts[2] = {1, tetrt::xcd_count(b->cus)};
     tm_trace_opts best = base;
     float best_ms = -1.0f;
     rc = TM_OK;
     for (int32_t blk : kBlocks) {
-        for (int32_t ch : kChunks) {
+        for (int32_t cand = 0; cand < 8 && rc == TM_OK; ++cand) {
+            const int32_t ch = kChunks[cand % 4];
             tm_trace_opts o = base;
             o.block = blk;
             o.sort = ch ? 2 : 1;
             o.sort_chunk_log2 = ch ? ch : base.sort_chunk_log2;
+            o.xcds = xcd_opts[cand / 4];
+            if (cand >= 4 && o.xcds == 1) continue;   // a device with one XCD
             if ((rc = set_jobs(b, n_jobs, jobs.data(), o, s)) != TM_OK) break;
             if ((e = enqueue(b, s)) != hipSuccess || (e = hipEventRecord(e0, s)) != hipSuccess) {
                 rc = hip_fail(e, "tm_batch_tune: launch");

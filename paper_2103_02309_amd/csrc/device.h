@@ -55,7 +55,8 @@ struct LaunchCfg {
     int32_t waves_per_simd; // persistent: resident waves per SIMD to launch for
     int32_t cus;            // compute units of the device
     int32_t grid_cap;       // persistent: at most this many blocks (0 = no cap)
-    int32_t xcds;           // one lane per ray: XCDs to give contiguous block ranges (1 = off)
+    int32_t xcds;           // one lane per ray: XCDs the blocks are renumbered for (1 = off)
+    int32_t xcd_blocks;     // consecutive blocks per XCD (0 = one contiguous range each)
     float eps;              // > 0: precision variant (one lane per ray)
 };
 
@@ -85,9 +86,10 @@ struct Job {
 };
 
 // One launch over all jobs (table in device memory, block0 ascending); jobs
-// share the record layout.  Rays without tmax get +inf.
+// share the record layout.  Rays without tmax get +inf.  xcds > 1: the blocks
+// are renumbered so that each XCD takes one contiguous range of them.
 hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_blocks, int32_t block,
-                              int32_t layout, hipStream_t s);
+                              int32_t layout, int32_t xcds, hipStream_t s);
 // Binning of every job's rays (chunks of 2^chunk_log2; perm pointers in the table).
 hipError_t launch_sort_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_chunks,
                              int32_t chunk_log2, hipStream_t s);

@@ -32,6 +32,9 @@ const char* last_error();
 // Record a printf-style message for tm_last_error and return code.
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int hip_fail(hipError_t e, const char* what);
+// Accelerator dies (XCDs) of a device with `cus` compute units: 32 CUs per XCD
+// on MI355X (256 CUs, 8 XCDs).
+inline int32_t xcd_count(int cus) { return cus >= 64 ? cus / 32 : 1; }
 // Binning configuration of a trace of n rays; *on = false when they are not binned.
 int sort_config(const tm_mesh_s* m, const tm_trace_opts& o, int64_t n, bool has_tmax, SortCfg* c,
                 bool* on);

@@ -572,6 +572,8 @@ struct Ray {
 
 struct Knobs {
     float eps;                // precision variant threshold (PREC kernels)
+    uint32_t xcd_blocks;      // block renumbering for the XCDs: 0 = one contiguous range per
+                              // XCD, > 0 = runs of this many consecutive blocks per XCD
 };
 
 __device__ __forceinline__ void write_result(const RayArgs& r, int64_t i, int32_t code, float t,
@@ -717,19 +719,32 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
 // is what hides the memory round trips.  The precision variant carries float64
 // code and settles for 4 waves rather than spilling.
 // The dispatcher deals blocks to the XCDs round-robin (block b runs on XCD
-// b mod X).  Renumbering so that each XCD gets one contiguous run of blocks
-// keeps neighbouring rays -- which visit the same tets -- on one L2.
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t X) {
+// b mod X), and each XCD has an L2 of its own.  Renumbering blocks so that
+// consecutive ones share an XCD keeps neighbouring rays -- which visit the same
+// tets, and read and write the same lines of the ray arrays -- on one L2.
+// G = 0: one contiguous range per XCD (the whole launch split X ways; walks of
+// uneven length then leave XCDs idle at the end).  G > 0: within each span of
+// X*G dispatched blocks, XCD x takes G consecutive blocks; a span is dispatched
+// at about the same time, so the balance of round-robin placement is kept.
+// Both are bijections on [0, nb); the blocks past the last whole span keep
+// their numbers.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t X, uint32_t G) {
     if (X <= 1) return b;
-    const uint32_t q = nb / X, rem = nb % X;
-    const uint32_t x = b % X, k = b / X;
-    return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+    if (G == 0) {
+        const uint32_t q = nb / X, rem = nb % X;
+        const uint32_t x = b % X, k = b / X;
+        return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+    }
+    const uint32_t span = X * G;
+    if (b >= nb / span * span) return b;
+    const uint32_t r = b % span;
+    return (b - r) + (r % X) * G + r / X;
 }
 
 template <bool TMAX, int LAYOUT, bool PREC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 4 : 8)))
 k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
-    const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds)) * blockDim.x + threadIdx.x;
+    const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds, kn.xcd_blocks)) * blockDim.x + threadIdx.x;
     if (j >= r.n) return;
     const int64_t i = r.perm ? int64_t(r.perm[j]) : j;
     if (uint64_t(i) >= uint64_t(r.n)) return;   // a caller's order that is no permutation
@@ -800,8 +815,8 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
 // descriptors are read with scalar loads); the rest is the walk of k_trace.
 template <int LAYOUT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
-k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs) {
-    const int64_t b = blockIdx.x;
+k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs, uint32_t xcds) {
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x, xcds, 0u);
     int lo = 0, hi = n_jobs;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -835,7 +850,8 @@ __global__ void __launch_bounds__(256) k_locate(DevMesh m, int64_t n, const floa
     const float px = pts[3 * i], py = pts[3 * i + 1], pz = pts[3 * i + 2];
     if (!isfinite(px + py + pz)) { out[i] = -1; return; }
     int32_t v[4];
-    const int32_t t = locate_point<LAYOUT, true>(m, M, px, py, pz, max_steps, 1e-6f, v);
+    int32_t t = locate_point<LAYOUT, true>(m, M, px, py, pz, max_steps, 1e-6f, v);
+    if (t >= 0) t = contain64<LAYOUT>(m, M, t, v, px, py, pz);
     out[i] = t >= 0 ? m.t_new2old[t] : (t == TM_RAY_STEP_CAP ? -2 : -1);
 }
 
@@ -853,10 +869,10 @@ void launch_trace_t(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipS
                            m, r, refill);
     } else if (c.eps > 0.0f) {
         hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, true>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m,
-                           r, uint32_t(std::max(1, c.xcds)), Knobs{c.eps});
+                           r, uint32_t(std::max(1, c.xcds)), Knobs{c.eps, uint32_t(c.xcd_blocks)});
     } else {
         hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, false>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m,
-                           r, uint32_t(std::max(1, c.xcds)), Knobs{0.0f});
+                           r, uint32_t(std::max(1, c.xcds)), Knobs{0.0f, uint32_t(c.xcd_blocks)});
     }
 }
 
@@ -878,15 +894,16 @@ hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, 
 }
 
 hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_blocks, int32_t block,
-                              int32_t layout, hipStream_t s) {
+                              int32_t layout, int32_t xcds, hipStream_t s) {
+    const uint32_t X = uint32_t(std::max(1, xcds));
     if (total_blocks <= 0 || n_jobs <= 0) return hipSuccess;
     const dim3 g{unsigned(total_blocks)}, b{unsigned(block)};
     if (layout == kTet16)
-        hipLaunchKernelGGL(k_trace_batch<kTet16>, g, b, 0, s, d_jobs, n_jobs);
+        hipLaunchKernelGGL(k_trace_batch<kTet16>, g, b, 0, s, d_jobs, n_jobs, X);
     else if (layout == kTet32N)
-        hipLaunchKernelGGL(k_trace_batch<kTet32N>, g, b, 0, s, d_jobs, n_jobs);
+        hipLaunchKernelGGL(k_trace_batch<kTet32N>, g, b, 0, s, d_jobs, n_jobs, X);
     else
-        hipLaunchKernelGGL(k_trace_batch<kTet20>, g, b, 0, s, d_jobs, n_jobs);
+        hipLaunchKernelGGL(k_trace_batch<kTet20>, g, b, 0, s, d_jobs, n_jobs, X);
     return hipGetLastError();
 }
 

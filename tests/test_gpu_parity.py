@@ -257,3 +257,46 @@ def test_binning_with_caller_workspace(tiny, tetrt):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
     with pytest.raises(tetrt.TetRTError):
         mesh.trace(_dev(o), _dev(d), sort=2, workspace=ws[: need // 2])
+
+
+@pytest.mark.parametrize("kw", [dict(xcds=8), dict(xcds=8, xcd_blocks=1), dict(xcds=8, xcd_blocks=4),
+                                dict(xcds=2, xcd_blocks=3, block=64), dict(xcds=8, xcd_blocks=8, sort=2)])
+def test_xcd_renumbering_changes_no_result(tiny, kw):
+    """Block renumbering for the XCDs only moves rays between lanes."""
+    m, om, mesh = tiny
+    o, d = random_interior_rays(40001, 53)
+    tm = np.random.default_rng(8).uniform(0.0, 0.6, 40001).astype(np.float32)
+    a = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), want_tets=True, want_steps=True, sort=1))
+    b = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), want_tets=True, want_steps=True, **kw))
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_caller_order(tiny, tetrt):
+    """tetmesh_bin_rays + order= gives the results of the call's own binning; an
+    order with entries out of range leaves those lanes idle."""
+    m, om, mesh = tiny
+    o, d = random_interior_rays(30001, 59)
+    tm = _dev(np.full(30001, 0.4, np.float32))
+    O, D = _dev(o), _dev(d)
+    a = _host(mesh.trace(O, D, tmax=tm, want_tets=True, want_steps=True, sort=1))
+    order = mesh.bin_rays(O, D, sort_chunk_log2=10)
+    got = np.sort(order.cpu().numpy())
+    assert np.array_equal(got, np.arange(30001))
+    b = _host(mesh.trace(O, D, tmax=tm, want_tets=True, want_steps=True, order=order))
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    rev = torch.arange(30000, -1, -1, dtype=torch.int32, device="cuda:0")
+    c = _host(mesh.trace(O, D, tmax=tm, want_tets=True, want_steps=True, order=rev))
+    for k in a:
+        assert np.array_equal(a[k], c[k], equal_nan=True), k
+    bad = rev.clone()
+    bad[:100] = 1 << 30                                 # out of range: those rays are skipped
+    out = mesh.trace(O, D, tmax=tm, order=bad)
+    out["tri"][:] = -9
+    mesh.trace_into(out, O, D, tmax=tm, order=bad)
+    h = _host(out)
+    skipped = np.arange(30000, 29900, -1)               # the rays the first 100 lanes would take
+    assert np.all(h["tri"][skipped] == -9)
+    rest = np.setdiff1d(np.arange(30001), skipped)
+    assert np.array_equal(h["tri"][rest], a["tri"][rest])

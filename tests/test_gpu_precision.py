@@ -32,9 +32,10 @@ def stress(tiny_mesh, tiny_oracle):
     mesh.free()
 
 
-def _run(mesh, o, d, eps):
-    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), want_steps=True,
-                     want_fp64=True, eps=eps, max_steps=20000)
+def _run(mesh, o, d, eps, start_tet=None):
+    st = None if start_tet is None else torch.from_numpy(start_tet).cuda()
+    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), start_tet=st,
+                     want_steps=True, want_fp64=True, eps=eps, max_steps=20000)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy() for k, v in res.items()}
 
@@ -52,6 +53,8 @@ def test_precision_sweep(stress, eps):
             "mismatch_rate": round(1.0 - rep["frac_identical"], 7),
             "unexplained": rep["n_unexplained"],
             "aborted": int((got["tri"][s] == -2).sum()),
+            "aborted_before_walk": int(((got["tri"][s] == -2) & (got["steps"][s] == 0)).sum()),
+            "invalid": int((got["tri"][s] == -3).sum()),
             "max_t_rel": rep["max_t_rel"],
             "rays_fp64": round(float((got["fp64_steps"][s] > 0).mean()), 5),
             "steps_fp64": round(float(got["fp64_steps"][s].sum() / max(1, got["steps"][s].clip(0).sum())), 6),
@@ -63,6 +66,16 @@ def test_precision_sweep(stress, eps):
             # with float32 rounding covered, every disagreement is an edge/vertex tie
             assert rep["n_unexplained"] == 0 and rep["gpu_abort_or_invalid"] == 0, (eps, name, rep)
             assert rep["max_t_rel"] <= 1e-5
+    if eps > 0.0:
+        # the same rays started in the oracle's located tets: separates location from walk
+        st = om.locate(o)
+        got2 = _run(mesh, o, d, eps, st)
+        s = kind == 2
+        rep2 = compare(m.points, om.tri_verts, o[s], d[s], {x: v[s] for x, v in ref.items()},
+                       {x: v[s] for x, v in got2.items()})
+        report["along edges, oracle start tets"] = {
+            "mismatch_rate": round(1.0 - rep2["frac_identical"], 7), "unexplained": rep2["n_unexplained"],
+            "aborted": int((got2["tri"][s] == -2).sum()), "invalid": int((got2["tri"][s] == -3).sum())}
     print("PRECISION " + json.dumps(report))
     if eps == 0.0:
         assert (got["fp64_steps"] == 0).all()
