@@ -234,11 +234,21 @@ __device__ __forceinline__ int exit_slot(float q0x, float q0y, float q1x, float 
 
 // Precision variant: threshold, the origin of the frame, and a count of the
 // steps decided in float64.
+// A float64 decision whose determinant is zero to within float64 rounding is a
+// tie: the ray meets a vertex or edge exactly, or lies in a face plane (a ray
+// along the mesh boundary).  Such ties are flagged (degen) so the ray can be
+// walked again from a slightly moved origin; allow_degen decides them by
+// Algorithm 1's plain inequalities instead.
 struct Prec {
     float eps;
     float ox, oy, oz;
     int32_t n64;
+    bool degen = false;
+    bool allow_degen = true;
 };
+
+// |det| of two float64 2-D points below this fraction of |a|_1 |b|_1: a tie
+constexpr double kTie64 = 1e-12;
 
 __device__ __forceinline__ double det2d(double ax, double ay, double bx, double by) {
     return __dmul_rn(ax, by) - __dmul_rn(ay, bx);
@@ -251,7 +261,7 @@ __device__ __forceinline__ void project64(const Frame& f, double pox, double poy
 }
 
 // Algorithm 1 on the float64 projections of the kept vertices a0..a2 and P.
-__device__ int exit_slot64(const Mem& M, const Frame& f, const Prec& pc, int32_t a0, int32_t a1,
+__device__ int exit_slot64(const Mem& M, const Frame& f, Prec& pc, int32_t a0, int32_t a1,
                            int32_t a2, float4 P) {
     const double pox = fma(double(f.ux), double(pc.ox), fma(double(f.uy), double(pc.oy), double(f.uz) * double(pc.oz)));
     const double poy = fma(double(f.vx), double(pc.ox), fma(double(f.vy), double(pc.oy), double(f.vz) * double(pc.oz)));
@@ -263,6 +273,12 @@ __device__ int exit_slot64(const Mem& M, const Frame& f, const Prec& pc, int32_t
     const double d0 = det2d(x3, y3, x0, y0);
     const double d1 = det2d(x3, y3, x1, y1);
     const double d2 = det2d(x3, y3, x2, y2);
+    if (!pc.allow_degen) {
+        const double s3 = fabs(x3) + fabs(y3);
+        pc.degen |= fabs(d0) <= kTie64 * s3 * (fabs(x0) + fabs(y0)) ||
+                    fabs(d1) <= kTie64 * s3 * (fabs(x1) + fabs(y1)) ||
+                    fabs(d2) <= kTie64 * s3 * (fabs(x2) + fabs(y2));
+    }
     return d0 < 0.0 ? (d2 >= 0.0 ? 1 : 0) : (d1 < 0.0 ? 2 : 0);
 }
 
@@ -296,7 +312,9 @@ __device__ __forceinline__ void make_ccw(Walk& w) {
 // its edges -- a ray along a mesh edge starts on two such faces -- has a
 // float32 orientation of random sign, and a wrongly oriented face misleads
 // every later exit decision.
-__device__ __forceinline__ void make_ccw64(const Frame& f, float Xx, float Xy, float Xz, float4 A,
+// Returns true when the orientation is a float64 tie (the face's projection is
+// a segment: its plane contains the ray direction).
+__device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, float Xz, float4 A,
                                            float4 B, float4 C, Walk& w) {
     const double pox = fma(double(f.ux), double(Xx), fma(double(f.uy), double(Xy), double(f.uz) * double(Xz)));
     const double poy = fma(double(f.vx), double(Xx), fma(double(f.vy), double(Xy), double(f.vz) * double(Xz)));
@@ -304,13 +322,16 @@ __device__ __forceinline__ void make_ccw64(const Frame& f, float Xx, float Xy, f
     project64(f, pox, poy, A, x0, y0);
     project64(f, pox, poy, B, x1, y1);
     project64(f, pox, poy, C, x2, y2);
-    const bool sw = det2d(x1 - x0, y1 - y0, x2 - x0, y2 - y0) < 0.0;
+    const double ex = x1 - x0, ey = y1 - y0, fx = x2 - x0, fy = y2 - y0;
+    const double o = det2d(ex, ey, fx, fy);
+    const bool sw = o < 0.0;
     const int32_t a1 = w.a1, a2 = w.a2;
     const float q1x = w.q1x, q1y = w.q1y, q2x = w.q2x, q2y = w.q2y, e1 = w.e1, e2 = w.e2;
     w.a1 = sw ? a2 : a1; w.a2 = sw ? a1 : a2;
     w.q1x = sw ? q2x : q1x; w.q2x = sw ? q1x : q2x;
     w.q1y = sw ? q2y : q1y; w.q2y = sw ? q1y : q2y;
     w.e1 = sw ? e2 : e1; w.e2 = sw ? e1 : e2;
+    return fabs(o) <= kTie64 * (fabs(ex) + fabs(ey)) * (fabs(fx) + fabs(fy));
 }
 
 // One step of the walk (Algorithm 1 with Algorithms 4-5 or 6-7), branch-free
@@ -363,7 +384,7 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
 template <bool DEPTH, int LAYOUT, typename T>
 __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const int32_t v[4],
                               float Xx, float Xy, float Xz, float Dx, float Dy, float Dz,
-                              const Frame& f, const Depth& g, Walk& w) {
+                              const Frame& f, const Depth& g, Walk& w, bool* degen = nullptr) {
     float4 P[4];
     T rx[4], ry[4], rz[4];
 #pragma unroll
@@ -416,10 +437,12 @@ __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const
                               : next_field<kTet20>(R, r, 0u, 0);
     if (LAYOUT == kTet32N) w.vxn = int32_t(pick4(R.w0, R.w1, R.w2, R.w3, r));
     w.cur = tet;
-    if (std::is_same<T, double>::value)
-        make_ccw64(f, Xx, Xy, Xz, PA, PB, PC, w);
-    else
+    if (std::is_same<T, double>::value) {
+        const bool tie = make_ccw64(f, Xx, Xy, Xz, PA, PB, PC, w);
+        if (degen) *degen = tie;
+    } else {
         make_ccw(w);
+    }
     return float(best);
 }
 
@@ -458,7 +481,7 @@ __device__ int32_t locate_point(const DevMesh& m, const Mem& M, float px, float 
     Walk w;
     using T = typename std::conditional<PREC, double, float>::type;
     const float s0 = start_in_tet<true, LAYOUT, T>(m, M, seed, v, Sx, Sy, Sz, Dx, Dy, Dz, f, g, w);
-    Prec pc{eps, Sx, Sy, Sz, 0};
+    Prec pc{eps, Sx, Sy, Sz, 0};   // ties decided by the plain inequalities
     if (!(s0 < 1.0f)) return seed;
     for (int32_t step = 0; step < max_steps; ++step) {
         const uint32_t field = w.next;
@@ -594,11 +617,15 @@ __device__ __forceinline__ void write_code(const RayArgs& r, int64_t i, int32_t 
 }
 
 // Set-up of ray i.  Returns true when the ray needs walking (state in s);
-// false when its result is already written.
+// false when its result is already written.  Precision variant: `moved`, when
+// given, replaces the ray's origin, and *degen reports a float64 tie in the
+// orientation of the start face.
 template <bool TMAX, int LAYOUT, bool PREC>
 __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, Ray& s,
-                          float eps) {
-    const float ox = r.orig[3 * i], oy = r.orig[3 * i + 1], oz = r.orig[3 * i + 2];
+                          float eps, const float* moved = nullptr, bool* degen = nullptr) {
+    const float ox = moved ? moved[0] : r.orig[3 * i];
+    const float oy = moved ? moved[1] : r.orig[3 * i + 1];
+    const float oz = moved ? moved[2] : r.orig[3 * i + 2];
     const float dx = r.dir[3 * i], dy = r.dir[3 * i + 1], dz = r.dir[3 * i + 2];
     s.tmax = (TMAX && r.tmax) ? r.tmax[i] : INFINITY;
     s.steps = 0;
@@ -631,10 +658,12 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
         project(s.f, PB, s.w.q1x, s.w.q1y);
         project(s.f, PC, s.w.q2x, s.w.q2y);
         if (TMAX) { s.w.e0 = depth(s.g, PA); s.w.e1 = depth(s.g, PB); s.w.e2 = depth(s.g, PC); }
-        if (PREC)
-            make_ccw64(s.f, ox, oy, oz, PA, PB, PC, s.w);
-        else
+        if (PREC) {
+            const bool tie = make_ccw64(s.f, ox, oy, oz, PA, PB, PC, s.w);
+            if (degen) *degen = tie;
+        } else {
             make_ccw(s.w);
+        }
         s.w.next = uint32_t(start);
         s.w.cur = int32_t(0x80000000u | uint32_t(sf));   // the start tet's field for this face
         return true;
@@ -656,7 +685,7 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
     set_origin(s.f, ox, oy, oz);
     if (TMAX) set_depth(s.g, dx, dy, dz, ox, oy, oz);
     using T = typename std::conditional<PREC, double, float>::type;
-    const float sx = start_in_tet<TMAX, LAYOUT, T>(m, M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w);
+    const float sx = start_in_tet<TMAX, LAYOUT, T>(m, M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w, degen);
     if (!(sx < INFINITY)) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
     return true;
 }
@@ -742,7 +771,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t 
 }
 
 template <bool TMAX, int LAYOUT, bool PREC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 4 : 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 3 : 8)))
 k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds, kn.xcd_blocks)) * blockDim.x + threadIdx.x;
     if (j >= r.n) return;
@@ -750,18 +779,50 @@ k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     if (uint64_t(i) >= uint64_t(r.n)) return;   // a caller's order that is no permutation
     const Mem M = make_mem<LAYOUT>(m);
     Ray s;
-    if (!setup_ray<TMAX, LAYOUT, PREC>(m, M, r, i, s, kn.eps)) return;
-    Prec pc{kn.eps, 0.0f, 0.0f, 0.0f, 0};
-    if (PREC) {
-        pc.ox = r.orig[3 * i];
-        pc.oy = r.orig[3 * i + 1];
-        pc.oz = r.orig[3 * i + 2];
+    if (!PREC) {
+        if (!setup_ray<TMAX, LAYOUT, false>(m, M, r, i, s, 0.0f)) return;
+        Prec pc{0.0f, 0.0f, 0.0f, 0.0f, 0};
+        while (walk_on<TMAX>(s, r.max_steps)) {
+            walk_step<TMAX, LAYOUT, false>(M, s.f, s.g, s.w, pc);
+            ++s.steps;
+        }
+        finish_ray<TMAX>(m, M, r, i, s);
+        return;
     }
-    while (walk_on<TMAX>(s, r.max_steps)) {
-        walk_step<TMAX, LAYOUT, PREC>(M, s.f, s.g, s.w, pc);
-        ++s.steps;
+    // Precision variant.  A ray whose walk meets a float64 tie is walked again
+    // from an origin moved by 1e-6 of the mesh extent towards the centre of the
+    // mesh bounds (and off the axes); the result keeps the given origin for t.
+    // Ties on the moved ray are decided by Algorithm 1's plain inequalities.
+    int32_t steps = 0, n64 = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        float moved[3] = {r.orig[3 * i], r.orig[3 * i + 1], r.orig[3 * i + 2]};
+        if (attempt == 1) {
+            float c[3], ext = 0.0f, len = 0.0f;
+            for (int a = 0; a < 3; ++a) {
+                const float span = float(m.G) / m.inv_cell[a];
+                ext = fmaxf(ext, span);
+                c[a] = m.lo[a] + 0.5f * span - moved[a];
+            }
+            const float tilt[3] = {0.0123f, 0.0457f, 0.0789f};
+            for (int a = 0; a < 3; ++a) len += c[a] * c[a];
+            const float il = len > 0.0f ? 1.0f / sqrtf(len) : 0.0f;
+            for (int a = 0; a < 3; ++a) moved[a] += 1e-6f * ext * (c[a] * il + tilt[a]);
+        }
+        bool degen = false;
+        if (!setup_ray<TMAX, LAYOUT, true>(m, M, r, i, s, kn.eps, attempt ? moved : nullptr, &degen)) return;
+        Prec pc{kn.eps, moved[0], moved[1], moved[2], 0};
+        pc.allow_degen = attempt == 1;
+        pc.degen = degen && attempt == 0;
+        while (!pc.degen && walk_on<TMAX>(s, r.max_steps - steps)) {
+            walk_step<TMAX, LAYOUT, true>(M, s.f, s.g, s.w, pc);
+            ++s.steps;
+        }
+        steps += s.steps;
+        n64 += pc.n64;
+        if (!pc.degen) break;
     }
-    finish_ray<TMAX>(m, M, r, i, s, pc.n64);
+    s.steps = steps;
+    finish_ray<TMAX>(m, M, r, i, s, n64);
 }
 
 // Persistent lanes: lane g of the grid owns the rays at positions g, g + L,
