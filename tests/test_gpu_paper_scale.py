@@ -15,12 +15,19 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def paper():
-    import paper_2103_02309_amd as tetrt
+def scene():
     m = config_mesh("paper")
-    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag)
     om = oracle.OracleMesh.from_kuhn(m)
     o, d, _ = pinhole_rays((0.5, 0.5, 0.02), 1920, 1080, 60.0, tile=8)
+    return m, om, o, d
+
+
+# Tet16 is the benchmark's layout; Tet20 is the paper's GPU layout
+@pytest.fixture(scope="module", params=["tet16", "tet20"])
+def paper(request, scene):
+    import paper_2103_02309_amd as tetrt
+    m, om, o, d = scene
+    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=request.param)
     res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), want_tets=True,
                      want_steps=True, block=256)
     torch.cuda.synchronize()
@@ -80,9 +87,10 @@ def test_ao_sampled_vs_oracle(paper):
     nrm, _ = tri_geometry(m.points, om.tri_verts[ref0["tri"][hit]])
     ao, ad, atm, parent = ao_rays(hp, nrm, d[idx][hit], k=8, seed=3, tmax=0.1)
     sf = ref0["tri"][hit][parent].astype(np.int32)
+    # binned, with the automatic die placement: the benchmark's AO launch
     res = mesh.trace(torch.from_numpy(ao).cuda(), torch.from_numpy(ad).cuda(),
                      tmax=torch.from_numpy(atm).cuda(), start_face=torch.from_numpy(sf).cuda(),
-                     want_tets=True, want_steps=True)
+                     want_tets=True, want_steps=True, sort=2)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in res.items()}
     ref = om.trace(ao, ad, atm, start_face=sf)
@@ -101,8 +109,13 @@ def test_ao_from_device_hits_properties(paper):
     nrm, _ = tri_geometry(m.points, mesh.tri_vertices(got["tri"][hit]))
     ao, ad, atm, parent = ao_rays(hp, nrm, d[hit], k=8, seed=3, tmax=0.1)
     sf = got["tri"][hit][parent].astype(np.int32)
-    res = mesh.trace(torch.from_numpy(ao).cuda(), torch.from_numpy(ad).cuda(),
-                     tmax=torch.from_numpy(atm).cuda(), start_face=torch.from_numpy(sf).cuda())
+    A = [torch.from_numpy(x).cuda() for x in (ao, ad, atm, sf)]
+    order = mesh.bin_rays(A[0], A[1])         # as the benchmark: binning, then the walk
+    res = mesh.trace(A[0], A[1], tmax=A[2], start_face=A[3], order=order)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in res.items()}
     _check_properties(m, mesh, ao, ad, g, atm)
+    # the call's own binning gives the same results
+    g2 = {k: v.cpu().numpy() for k, v in mesh.trace(A[0], A[1], tmax=A[2], start_face=A[3]).items()}
+    for k in g:
+        assert np.array_equal(g[k], g2[k], equal_nan=True), k
