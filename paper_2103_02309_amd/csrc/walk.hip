@@ -247,8 +247,11 @@ struct Prec {
     bool allow_degen = true;
 };
 
-// |det| of two float64 2-D points below this fraction of |a|_1 |b|_1: a tie
-constexpr double kTie64 = 1e-12;
+// A float64 projection of a point carries an absolute error of a few units of
+// float64 rounding of the coordinates (about 1e-16 of the scene's size S), so a
+// determinant of two projected points a, b is decided to within
+// 1e-16 S (|a|_1 + |b|_1); anything within 1e-14 S (|a|_1 + |b|_1) is a tie.
+constexpr double kTie64 = 1e-14;
 
 __device__ __forceinline__ double det2d(double ax, double ay, double bx, double by) {
     return __dmul_rn(ax, by) - __dmul_rn(ay, bx);
@@ -274,10 +277,11 @@ __device__ int exit_slot64(const Mem& M, const Frame& f, Prec& pc, int32_t a0, i
     const double d1 = det2d(x3, y3, x1, y1);
     const double d2 = det2d(x3, y3, x2, y2);
     if (!pc.allow_degen) {
+        const double S = kTie64 * (1.0 + fabs(pox) + fabs(poy));
         const double s3 = fabs(x3) + fabs(y3);
-        pc.degen |= fabs(d0) <= kTie64 * s3 * (fabs(x0) + fabs(y0)) ||
-                    fabs(d1) <= kTie64 * s3 * (fabs(x1) + fabs(y1)) ||
-                    fabs(d2) <= kTie64 * s3 * (fabs(x2) + fabs(y2));
+        pc.degen |= fabs(d0) <= S * (s3 + fabs(x0) + fabs(y0)) ||
+                    fabs(d1) <= S * (s3 + fabs(x1) + fabs(y1)) ||
+                    fabs(d2) <= S * (s3 + fabs(x2) + fabs(y2));
     }
     return d0 < 0.0 ? (d2 >= 0.0 ? 1 : 0) : (d1 < 0.0 ? 2 : 0);
 }
@@ -331,7 +335,7 @@ __device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, f
     w.q1x = sw ? q2x : q1x; w.q2x = sw ? q1x : q2x;
     w.q1y = sw ? q2y : q1y; w.q2y = sw ? q1y : q2y;
     w.e1 = sw ? e2 : e1; w.e2 = sw ? e1 : e2;
-    return fabs(o) <= kTie64 * (fabs(ex) + fabs(ey)) * (fabs(fx) + fabs(fy));
+    return fabs(o) <= kTie64 * (1.0 + fabs(pox) + fabs(poy)) * (fabs(ex) + fabs(ey) + fabs(fx) + fabs(fy));
 }
 
 // One step of the walk (Algorithm 1 with Algorithms 4-5 or 6-7), branch-free
@@ -618,11 +622,13 @@ __device__ __forceinline__ void write_code(const RayArgs& r, int64_t i, int32_t 
 
 // Set-up of ray i.  Returns true when the ray needs walking (state in s);
 // false when its result is already written.  Precision variant: `moved`, when
-// given, replaces the ray's origin, and *degen reports a float64 tie in the
-// orientation of the start face.
+// given, replaces the ray's origin, *degen reports a float64 tie in the
+// orientation of the start face, and *lost that no start tet was found (the
+// origin lies on the mesh boundary, or no face of the start tet faces the ray).
 template <bool TMAX, int LAYOUT, bool PREC>
 __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, Ray& s,
-                          float eps, const float* moved = nullptr, bool* degen = nullptr) {
+                          float eps, const float* moved = nullptr, bool* degen = nullptr,
+                          bool* lost = nullptr) {
     const float ox = moved ? moved[0] : r.orig[3 * i];
     const float oy = moved ? moved[1] : r.orig[3 * i + 1];
     const float oz = moved ? moved[2] : r.orig[3 * i + 2];
@@ -678,7 +684,11 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
         v[0] = sv.x; v[1] = sv.y; v[2] = sv.z; v[3] = sv.w;
     } else {
         tet = locate_point<LAYOUT, PREC>(m, M, ox, oy, oz, r.max_steps, eps, v);
-        if (tet < 0) { write_code(r, i, tet, 0); return false; }
+        if (tet < 0) {
+            if (lost) *lost = true;
+            write_code(r, i, tet, 0);
+            return false;
+        }
     }
     if (PREC) tet = contain64<LAYOUT>(m, M, tet, v, ox, oy, oz);
     specialized_basis(dx, dy, dz, s.f);
@@ -686,7 +696,11 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
     if (TMAX) set_depth(s.g, dx, dy, dz, ox, oy, oz);
     using T = typename std::conditional<PREC, double, float>::type;
     const float sx = start_in_tet<TMAX, LAYOUT, T>(m, M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w, degen);
-    if (!(sx < INFINITY)) { write_code(r, i, TM_RAY_INVALID, 0); return false; }
+    if (!(sx < INFINITY)) {
+        if (lost) *lost = true;
+        write_code(r, i, TM_RAY_INVALID, 0);
+        return false;
+    }
     return true;
 }
 
@@ -808,8 +822,11 @@ k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
             const float il = len > 0.0f ? 1.0f / sqrtf(len) : 0.0f;
             for (int a = 0; a < 3; ++a) moved[a] += 1e-6f * ext * (c[a] * il + tilt[a]);
         }
-        bool degen = false;
-        if (!setup_ray<TMAX, LAYOUT, true>(m, M, r, i, s, kn.eps, attempt ? moved : nullptr, &degen)) return;
+        bool degen = false, lost = false;
+        if (!setup_ray<TMAX, LAYOUT, true>(m, M, r, i, s, kn.eps, attempt ? moved : nullptr, &degen, &lost)) {
+            if (attempt == 0 && lost) continue;   // an origin on the boundary: move it inwards
+            return;
+        }
         Prec pc{kn.eps, moved[0], moved[1], moved[2], 0};
         pc.allow_degen = attempt == 1;
         pc.degen = degen && attempt == 0;
