@@ -28,6 +28,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane per
+# cycle (an FMA counted once; no packed FP32) = 39.3 T lane-operations/s
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic operations of one walk step (the method's arithmetic and bookkeeping,
+# counted per ray): fourth vertex id 3 xor; projection of the new point (Eq. 3-5) 8;
+# Algorithm 1: two 2-D determinants and two sign tests 8; exit vertex 1; its rank
+# among the four ids 5; neighbour read 1; face update 3; termination test 1 = 30.
+# Tet16 (Algorithms 6-7) adds the rank of the new vertex 5, one more read and 2 xor;
+# Tet32N one more read.  With tmax: the new point's depth 3, its slot 1, min of the
+# face's depths and the test 3.
+ALG_OPS_STEP = {"tet20": 30, "tet16": 38, "tet32n": 31}
+ALG_OPS_TMAX = 7
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_ao_rays_12.6M_tets_hbm_traffic.md")
 # algorithmic bytes of one walk step: the fields the step needs, whatever the layout --
 # the xor field (4 B), one neighbour field (4 B) and the new point (12 B)
 STEP_BYTES = 20
@@ -203,10 +216,14 @@ def main():
     # algorithmic bytes per launch: per-ray I/O plus 20 B per walk step
     bytes_p = int(steps_p.sum()) * STEP_BYTES + n_p * RAY_IO_BYTES
     bytes_a = int(steps_a.sum()) * STEP_BYTES + n_a * (RAY_IO_BYTES + 2 * OPT_INPUT_BYTES)
-    kern = {"primary": (ms_p.mean(), bytes_p, n_p), "ao": (ms_a.mean(), bytes_a, n_a)}
+    ops_p = int(steps_p.sum()) * ALG_OPS_STEP[args.layout]
+    ops_a = int(steps_a.sum()) * (ALG_OPS_STEP[args.layout] + ALG_OPS_TMAX)
+    kern = {"primary": (ms_p.mean(), bytes_p, ops_p), "ao": (ms_a.mean(), bytes_a, ops_a)}
     dom = max(kern, key=lambda k: kern[k][0])
-    dom_ms, dom_bytes, dom_rays = kern[dom]
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    dom_ms, dom_bytes, dom_ops = kern[dom]
+    achieved = dom_ops / (dom_ms * 1e-3) / 1e12
+    alg_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args) if dom == "ao" else None
 
     line = {
         "metric": "closest-hit Mrays/s at 12.6M tets",
@@ -232,10 +249,15 @@ def main():
             "ray_binning": {0: "auto (AO rays)", 1: "off", 2: "on"}[args.sort], "eye": list(eye),
         },
         "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            # the walk is bound by VALU issue (counters: 92-100% busy), not by HBM
+            "bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TOPS, 2),
+            "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
             "kernel": "k_trace (%s rays)" % dom, "kernel_ms": round(float(dom_ms), 4),
-            "algorithmic_bytes": dom_bytes,
+            "algorithmic_ops": dom_ops, "algorithmic_bytes": dom_bytes,
+            "algorithmic_gbs": round(alg_gbs, 1), "hbm_peak_gbs": HBM_PEAK_GBS,
+            "hbm_frac_algorithmic": round(alg_gbs / HBM_PEAK_GBS, 4),
+            "hbm_frac_measured": (round(traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                  if traffic else None),
         },
         "detail": {
             "primary_ms": round(float(ms_p.mean()), 4), "ao_ms": round(float(ms_a.mean()), 4),
@@ -259,6 +281,40 @@ def main():
         line["cpu_baseline"] = cpu_baseline(m, o, d, ao, ad, atm, sf, parent, hit, args.cpu_stride, log)
     mesh.free()
     print(json.dumps(line), flush=True)
+
+
+def kernel_source_hash():
+    """sha256 of the walk kernel's sources, to tell whether a counter summary
+    still describes the kernel that runs."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("walk.hip", "device.h"):
+        with open(os.path.join(ROOT, "paper_2103_02309_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(args):
+    """HBM bytes per launch of the AO walk, from the committed rocprofv3 counter
+    summary (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scaled by a device copy), or
+    None when the summary was taken on other kernel sources or another setup."""
+    if args.layout != "tet16" or args.sfc != "hilbert" or args.sort != 0 or args.block != 256:
+        return None
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if "=" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
+            k, v = line.strip().strip("`").split("=", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def bench_batch(args, tetrt, dev, log):

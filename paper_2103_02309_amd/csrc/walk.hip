@@ -398,6 +398,16 @@ __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const
         ry[k] = T(P[k].y) - T(Xy);
         rz[k] = T(P[k].z) - T(Xz);
     }
+    // In float64 (precision variant) the plane tests use the direction the walk
+    // actually projects along, u x v of the float32 basis, rather than D: the two
+    // differ by float32 rounding, and for a ray that grazes an edge the start face
+    // chosen for D need not surround the origin in the walk's projection.
+    T ex = T(Dx), ey = T(Dy), ez = T(Dz);
+    if (std::is_same<T, double>::value) {
+        ex = T(f.uy) * T(f.vz) - T(f.uz) * T(f.vy);
+        ey = T(f.uz) * T(f.vx) - T(f.ux) * T(f.vz);
+        ez = T(f.ux) * T(f.vy) - T(f.uy) * T(f.vx);
+    }
     T best = T(INFINITY);
     int bj = -1;
 #pragma unroll
@@ -412,7 +422,7 @@ __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const
         T nz = e1x * e2y - e1y * e2x;
         const T side = nx * (rx[j] - rx[A]) + ny * (ry[j] - ry[A]) + nz * (rz[j] - rz[A]);
         if (side > T(0)) { nx = -nx; ny = -ny; nz = -nz; }
-        const T nd = nx * T(Dx) + ny * T(Dy) + nz * T(Dz);
+        const T nd = nx * ex + ny * ey + nz * ez;
         if (nd > T(0)) {
             const T s = (nx * rx[A] + ny * ry[A] + nz * rz[A]) / nd;
             if (s < best) { best = s; bj = j; }

@@ -45,6 +45,13 @@ def test_precision_sweep(stress, eps):
     m, om, mesh, o, d, kind, ref = stress
     got = _run(mesh, o, d, eps)
     report = {"eps": eps, "rays": int(len(o))}
+    bad = np.nonzero(got["tri"] == -2)[0][:12]
+    if bad.size:
+        # the rays that ended at the step cap, for diagnosis
+        print("PRECISION_CAP " + json.dumps({"eps": eps, "rays": [
+            {"i": int(k), "kind": int(kind[k]), "o": o[k].tolist(), "d": d[k].tolist(),
+             "steps": int(got["steps"][k]), "fp64": int(got["fp64_steps"][k]),
+             "ref_tri": int(ref["tri"][k]), "ref_steps": int(ref["steps"][k])} for k in bad]}))
     for k, name in KINDS.items():
         s = kind == k
         rep = compare(m.points, om.tri_verts, o[s], d[s], {x: v[s] for x, v in ref.items()},
