@@ -136,6 +136,22 @@ __device__ __forceinline__ uint32_t pick4(uint32_t w0, uint32_t w1, uint32_t w2,
     return b1 ? hi : lo;
 }
 
+// Per-lane conditions as wave lane masks: a comparison becomes a 64-bit mask in
+// scalar registers, masks combine with scalar ALU operations (and, or, xor on
+// whole wavefronts), and a mask turns back into a per-lane condition for a
+// vector select at no vector cost.  Used inside the walk, where every lane of
+// the wave that is still active runs the same code.
+__device__ __forceinline__ uint64_t lanes(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+__device__ __forceinline__ bool lane(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// Word (hi, lo) of four: word 2*hi + lo (three vector selects).
+__device__ __forceinline__ uint32_t pick4b(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, bool lo,
+                                           bool hi) {
+    const uint32_t a = lo ? w1 : w0;
+    const uint32_t b = lo ? w3 : w2;
+    return hi ? b : a;
+}
+
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t next_field(const Rec& R, int r, uint32_t back, int ra) {
     if (LAYOUT == kTet16) {
@@ -349,8 +365,14 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
     const float4 P = load_pt(M, uint32_t(id3));
     float q3x, q3y;
     project(f, P, q3x, q3y);
-    int e = exit_slot(w.q0x, w.q0y, w.q1x, w.q1y, w.q2x, w.q2y, q3x, q3y);
+    // Algorithm 1 as lane masks: the exit face drops slot 1 when det(q3,q0) < 0 and
+    // det(q3,q2) >= 0, slot 2 when det(q3,q0) >= 0 and det(q3,q1) < 0, else slot 0
+    const bool n0 = det2(q3x, q3y, w.q0x, w.q0y) < 0.0f;
+    const bool n1 = det2(q3x, q3y, w.q1x, w.q1y) < 0.0f;
+    const bool p2 = det2(q3x, q3y, w.q2x, w.q2y) >= 0.0f;
+    bool s1 = n0 & p2, s2 = !n0 & n1;
     if (PREC) {
+        int e = s1 ? 1 : (s2 ? 2 : 0);
         const float s3 = fabsf(q3x) + fabsf(q3y);
         const bool unsure =
             fabsf(det2(q3x, q3y, w.q0x, w.q0y)) <= pc.eps * (s3 + fabsf(w.q0x) + fabsf(w.q0y)) ||
@@ -360,15 +382,28 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
             e = exit_slot64(M, f, pc, w.a0, w.a1, w.a2, P);
             ++pc.n64;
         }
+        s1 = e == 1;
+        s2 = e == 2;
     }
-    const bool s0 = e == 0, s1 = e == 1;
-    const int32_t x = s0 ? w.a0 : (s1 ? w.a1 : w.a2);
-    const int r = (w.a0 < x) + (w.a1 < x) + (w.a2 < x) + (id3 < x);
-    const int ra = LAYOUT == kTet16 ? (w.a0 < id3) + (w.a1 < id3) + (w.a2 < id3) : 0;
-    w.next = next_field<LAYOUT>(R, r, uint32_t(w.cur), ra);
-    if (LAYOUT == kTet32N) w.vxn = int32_t(pick4(R.w0, R.w1, R.w2, R.w3, r));
+    const bool s0 = !(s1 | s2);
+    const int32_t x = s1 ? w.a1 : (s2 ? w.a2 : w.a0);
+    // rank of the exit vertex x among the tet's four ids (Algorithms 4-5), as its
+    // two bits: the count of ids below x is odd (lo) / at least 2 (hi)
+    const uint64_t b0 = lanes(w.a0 < x), b1 = lanes(w.a1 < x), b2 = lanes(w.a2 < x), b3 = lanes(id3 < x);
+    const bool rlo = lane(b0 ^ b1 ^ b2 ^ b3);
+    const bool rhi = lane(((b0 | b1) & (b2 | b3)) | (b0 & b1) | (b2 & b3));
+    if (LAYOUT == kTet16) {
+        // Algorithms 6-7: next = prev ^ NX[rank of id3] ^ NX[rank of x], NX3 = 0
+        const uint64_t c0 = lanes(w.a0 < id3), c1 = lanes(w.a1 < id3), c2 = lanes(w.a2 < id3);
+        const bool alo = lane(c0 ^ c1 ^ c2);
+        const bool ahi = lane((c0 & c1) | (c2 & (c0 | c1)));
+        w.next = uint32_t(w.cur) ^ pick4b(R.n0, R.n1, R.n2, 0u, alo, ahi) ^
+                 pick4b(R.n0, R.n1, R.n2, 0u, rlo, rhi);
+    } else {
+        w.next = pick4b(R.n0, R.n1, R.n2, R.n3, rlo, rhi);
+    }
+    if (LAYOUT == kTet32N) w.vxn = int32_t(pick4b(R.w0, R.w1, R.w2, R.w3, rlo, rhi));
     w.cur = int32_t(tet);
-    const bool s2 = !(s0 | s1);
     w.a0 = s0 ? id3 : w.a0;  w.q0x = s0 ? q3x : w.q0x;  w.q0y = s0 ? q3y : w.q0y;
     w.a1 = s1 ? id3 : w.a1;  w.q1x = s1 ? q3x : w.q1x;  w.q1y = s1 ? q3y : w.q1y;
     w.a2 = s2 ? id3 : w.a2;  w.q2x = s2 ? q3x : w.q2x;  w.q2y = s2 ? q3y : w.q2y;
