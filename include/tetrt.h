@@ -284,9 +284,10 @@ int tm_batch_create(int32_t max_jobs, int64_t max_rays, tm_batch* out);
 
 /* tm_batch_set -- replace the batch's jobs.  jobs host [n_jobs] (0 <= n_jobs <=
  * max_jobs), copied.  opts as for trace_closest, except: kernel 0 or 1, eps = 0,
- * xcd_blocks, refill, grid_cap, workspace, fp64_steps and order are ignored, and the binning
- * chunk size is one for all jobs (sort = 0 bins the jobs that carry tmax and
- * have at least 2^18 rays).  The new table is copied to the device on
+ * xcd_blocks, refill, grid_cap, workspace, fp64_steps and order are ignored,
+ * xcds = 0 means round-robin placement (xcds > 1: one contiguous range of the
+ * whole launch per XCD), and the binning chunk size is one for all jobs
+ * (sort = 0 bins the jobs that carry tmax and have at least 2^18 rays).  The new table is copied to the device on
  * hip_stream, after the batch's previous table copy has left the staging
  * buffer; launches on that stream that follow see it.  A launch of the batch on
  * another stream must be ordered after this call's stream by the caller.

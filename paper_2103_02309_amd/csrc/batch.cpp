@@ -146,8 +146,10 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
     shape->layout = layout < 0 ? 0 : layout;
     shape->blocks = blocks;
     shape->chunks = chunks;
-    // automatic as in trace_closest: one contiguous range per XCD when rays are binned
-    shape->xcds = o.xcds ? o.xcds : (chunks > 0 ? tetrt::xcd_count(b->cus) : 1);
+    // automatic: round-robin placement.  One contiguous range per XCD over a
+    // whole batch splits jobs of unequal walks unevenly over the XCDs (measured
+    // slower on many-mesh batches); the tuner tries it
+    shape->xcds = o.xcds ? o.xcds : 1;
     return TM_OK;
 }
 
