@@ -211,7 +211,9 @@ int step(tm_server_s* s, hipStream_t stream, int64_t* launched) {
         j.n_rays = q.n;
         j.d_orig = s->pool.orig + 3 * q.base;
         j.d_dir = s->pool.dir + 3 * q.base;
-        j.d_tmax = s->pool.tmax + q.base;
+        // camera rays carry no tmax (so the automatic rule leaves them unbinned, as
+        // primary rays gain nothing from binning); secondary rays do
+        j.d_tmax = q.st == St::Pending0 ? nullptr : s->pool.tmax + q.base;
         j.d_start_face = s->pool.sf + q.base;
         if (final_phase) {
             j.d_tri = q.r.d_tri;
