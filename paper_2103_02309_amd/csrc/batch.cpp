@@ -25,9 +25,10 @@ constexpr int64_t kPermAlign = 64;  // ints; each binned job's permutation start
 struct Shape {
     int32_t n_jobs = -1, block = 0, chunk_log2 = 0, layout = -1, xcds = 1;
     int64_t blocks = -1, chunks = -1;
+    bool steps = false;   // some job asks for step counts
     bool operator==(const Shape& o) const {
         return n_jobs == o.n_jobs && block == o.block && chunk_log2 == o.chunk_log2 && layout == o.layout &&
-               xcds == o.xcds && blocks == o.blocks && chunks == o.chunks;
+               xcds == o.xcds && blocks == o.blocks && chunks == o.chunks && steps == o.steps;
     }
 };
 
@@ -128,6 +129,7 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
         r.bary = j.d_bary;
         r.hit_tets = j.d_hit_tets;
         r.steps = j.d_steps;
+        if (j.d_steps && j.n_rays > 0) shape->steps = true;
         r.fp64_steps = nullptr;
         r.n = j.n_rays;
         r.max_steps = o.max_steps > 0 ? o.max_steps : 65536;
@@ -184,7 +186,8 @@ hipError_t enqueue(const tm_batch_s* b, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (sh.chunks > 0) e = tetrt::launch_sort_batch(b->d_table, sh.n_jobs, sh.chunks, sh.chunk_log2, s);
     if (e != hipSuccess) return e;
-    return tetrt::launch_trace_batch(b->d_table, sh.n_jobs, sh.blocks, sh.block, sh.layout, sh.xcds, s);
+    return tetrt::launch_trace_batch(b->d_table, sh.n_jobs, sh.blocks, sh.block, sh.layout, sh.xcds, sh.steps,
+                                     s);
 }
 
 int check_batch(const tm_batch_s* b, const char* what) {

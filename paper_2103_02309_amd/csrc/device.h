@@ -87,9 +87,10 @@ struct Job {
 
 // One launch over all jobs (table in device memory, block0 ascending); jobs
 // share the record layout.  Rays without tmax get +inf.  xcds > 1: the blocks
-// are renumbered so that each XCD takes one contiguous range of them.
+// are renumbered so that each XCD takes one contiguous range of them.  steps:
+// some job has a step-count array (the kernel then keeps per-ray counts).
 hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_blocks, int32_t block,
-                              int32_t layout, int32_t xcds, hipStream_t s);
+                              int32_t layout, int32_t xcds, bool steps, hipStream_t s);
 // Binning of every job's rays (chunks of 2^chunk_log2; perm pointers in the table).
 hipError_t launch_sort_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_chunks,
                              int32_t chunk_log2, hipStream_t s);

@@ -54,6 +54,24 @@
 #include "device.h"
 #include "tetrt.h"
 
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Structured buffer loads (index * stride + offset, computed by the address
+// unit): a record or point is read by its id, with no vector instruction to
+// scale the id into a byte offset.  Clang has builtins for the raw (byte
+// offset) forms only, so these name the LLVM intrinsics directly.
+extern "C" __device__ u32x4 sbuf_load_b128(rsrc_t r, unsigned index, unsigned voffset,
+                                           unsigned soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
+extern "C" __device__ u32x3 sbuf_load_b96(rsrc_t r, unsigned index, unsigned voffset,
+                                          unsigned soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v3i32");
+extern "C" __device__ unsigned sbuf_load_b32(rsrc_t r, unsigned index, unsigned voffset,
+                                             unsigned soffset, int aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.i32");
+
 namespace tetrt {
 
 namespace {
@@ -69,12 +87,12 @@ constexpr int kTet32N = 2;
 template <int LAYOUT>
 constexpr uint32_t rec_bytes() { return LAYOUT == kTet20 ? 20u : (LAYOUT == kTet16 ? 16u : 32u); }
 
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-
-// gfx9-family buffer descriptor, raw (stride 0) addressing, bounds = byte size
-__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint64_t bytes) {
-    const uint32_t n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : uint32_t(bytes);
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(n), 0x00020000);
+// gfx9-family buffer descriptor for `count` elements of `stride` bytes.  An
+// access to an index at or past `count` reads zeros (the bound is given in
+// elements, the unit the address unit checks an index against when the stride
+// is non-zero).
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t stride, uint32_t count) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)stride, int(count), 0x00020000);
 }
 
 struct Mem {
@@ -85,8 +103,8 @@ struct Mem {
 template <int LAYOUT>
 __device__ __forceinline__ Mem make_mem(const DevMesh& m) {
     Mem M;
-    M.rec = make_rsrc(m.rec, uint64_t(m.nt) * rec_bytes<LAYOUT>());
-    M.pts = make_rsrc(m.pts, uint64_t(m.np) * 16u);
+    M.rec = make_rsrc(m.rec, rec_bytes<LAYOUT>(), uint32_t(m.nt));
+    M.pts = make_rsrc(m.pts, 16u, uint32_t(m.np));
     return M;
 }
 
@@ -107,19 +125,16 @@ struct Rec {
 template <int LAYOUT>
 __device__ __forceinline__ Rec load_rec(const Mem& M, uint32_t tet) {
     if (LAYOUT == kTet20) {
-        uint32_t t4 = tet << 2;   // 20 * tet as two shifts, not a quarter-rate multiply
-        keep(t4);
-        const uint32_t off = (tet << 4) + t4;
-        const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, off, 0, 0);
-        uint32_t b = __builtin_amdgcn_raw_buffer_load_b32(M.rec, off + 16u, 0, 0);
+        const u32x4 a = sbuf_load_b128(M.rec, tet, 0u, 0u, 0);
+        uint32_t b = sbuf_load_b32(M.rec, tet, 16u, 0u, 0);
         keep(b);
         return Rec{int32_t(a[0]), a[1], a[2], a[3], b, 0u, 0u, 0u, 0u};
     } else if (LAYOUT == kTet16) {
-        const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, tet << 4, 0, 0);
+        const u32x4 a = sbuf_load_b128(M.rec, tet, 0u, 0u, 0);
         return Rec{int32_t(a[0]), a[1], a[2], a[3], 0u, 0u, 0u, 0u, 0u};
     } else {
-        const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.rec, tet << 5, 0, 0);
-        const auto b = __builtin_amdgcn_raw_buffer_load_b128(M.rec, (tet << 5) + 16u, 0, 0);
+        const u32x4 a = sbuf_load_b128(M.rec, tet, 0u, 0u, 0);
+        const u32x4 b = sbuf_load_b128(M.rec, tet, 16u, 0u, 0);
         return Rec{0, a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
     }
 }
@@ -162,7 +177,7 @@ __device__ __forceinline__ uint32_t next_field(const Rec& R, int r, uint32_t bac
 }
 
 __device__ __forceinline__ float4 load_pt(const Mem& M, uint32_t id) {
-    const auto a = __builtin_amdgcn_raw_buffer_load_b128(M.pts, id * 16u, 0, 0);
+    const u32x3 a = sbuf_load_b96(M.pts, id, 0u, 0u, 0);
     return make_float4(__uint_as_float(a[0]), __uint_as_float(a[1]), __uint_as_float(a[2]), 0.0f);
 }
 
@@ -356,7 +371,11 @@ __device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, f
 
 // One step of the walk (Algorithm 1 with Algorithms 4-5 or 6-7), branch-free
 // (apart from the rare float64 re-evaluation of the precision variant).
-template <bool DEPTH, int LAYOUT, bool PREC>
+// LINK (Tet16): w.cur carries the xor of the previous tet's field and w.next
+// instead of the field itself, before and after the step.  The step then
+// updates both in place (w.cur ^= NX[a] ^ NX[b], w.next ^= w.cur) rather than
+// rotating previous / current / next through registers.
+template <bool DEPTH, int LAYOUT, bool PREC, bool LINK = false>
 __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const Depth& g, Walk& w,
                                           Prec& pc) {
     const uint32_t tet = w.next;
@@ -367,12 +386,12 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
     project(f, P, q3x, q3y);
     // Algorithm 1 as lane masks: the exit face drops slot 1 when det(q3,q0) < 0 and
     // det(q3,q2) >= 0, slot 2 when det(q3,q0) >= 0 and det(q3,q1) < 0, else slot 0
-    const bool n0 = det2(q3x, q3y, w.q0x, w.q0y) < 0.0f;
-    const bool n1 = det2(q3x, q3y, w.q1x, w.q1y) < 0.0f;
-    const bool p2 = det2(q3x, q3y, w.q2x, w.q2y) >= 0.0f;
-    bool s1 = n0 & p2, s2 = !n0 & n1;
+    const uint64_t N0 = lanes(det2(q3x, q3y, w.q0x, w.q0y) < 0.0f);
+    const uint64_t N1 = lanes(det2(q3x, q3y, w.q1x, w.q1y) < 0.0f);
+    const uint64_t P2 = lanes(det2(q3x, q3y, w.q2x, w.q2y) >= 0.0f);
+    uint64_t S1 = N0 & P2, S2 = N1 & ~N0;
     if (PREC) {
-        int e = s1 ? 1 : (s2 ? 2 : 0);
+        int e = lane(S1) ? 1 : (lane(S2) ? 2 : 0);
         const float s3 = fabsf(q3x) + fabsf(q3y);
         const bool unsure =
             fabsf(det2(q3x, q3y, w.q0x, w.q0y)) <= pc.eps * (s3 + fabsf(w.q0x) + fabsf(w.q0y)) ||
@@ -382,10 +401,10 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
             e = exit_slot64(M, f, pc, w.a0, w.a1, w.a2, P);
             ++pc.n64;
         }
-        s1 = e == 1;
-        s2 = e == 2;
+        S1 = lanes(e == 1);
+        S2 = lanes(e == 2);
     }
-    const bool s0 = !(s1 | s2);
+    const bool s1 = lane(S1), s2 = lane(S2), s0 = lane(~(S1 | S2));
     const int32_t x = s1 ? w.a1 : (s2 ? w.a2 : w.a0);
     // rank of the exit vertex x among the tet's four ids (Algorithms 4-5), as its
     // two bits: the count of ids below x is odd (lo) / at least 2 (hi)
@@ -397,13 +416,20 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
         const uint64_t c0 = lanes(w.a0 < id3), c1 = lanes(w.a1 < id3), c2 = lanes(w.a2 < id3);
         const bool alo = lane(c0 ^ c1 ^ c2);
         const bool ahi = lane((c0 & c1) | (c2 & (c0 | c1)));
-        w.next = uint32_t(w.cur) ^ pick4b(R.n0, R.n1, R.n2, 0u, alo, ahi) ^
-                 pick4b(R.n0, R.n1, R.n2, 0u, rlo, rhi);
+        const uint32_t xa = pick4b(R.n0, R.n1, R.n2, 0u, alo, ahi);
+        const uint32_t xb = pick4b(R.n0, R.n1, R.n2, 0u, rlo, rhi);
+        if (LINK) {
+            w.cur = int32_t(uint32_t(w.cur) ^ xa ^ xb);   // prev ^ tet ^ NX[a] ^ NX[b] = tet ^ next
+            w.next = uint32_t(w.cur) ^ tet;
+        } else {
+            w.next = uint32_t(w.cur) ^ xa ^ xb;
+            w.cur = int32_t(tet);
+        }
     } else {
         w.next = pick4b(R.n0, R.n1, R.n2, R.n3, rlo, rhi);
+        w.cur = int32_t(tet);
     }
     if (LAYOUT == kTet32N) w.vxn = int32_t(pick4b(R.w0, R.w1, R.w2, R.w3, rlo, rhi));
-    w.cur = int32_t(tet);
     w.a0 = s0 ? id3 : w.a0;  w.q0x = s0 ? q3x : w.q0x;  w.q0y = s0 ? q3y : w.q0y;
     w.a1 = s1 ? id3 : w.a1;  w.q1x = s1 ? q3x : w.q1x;  w.q1y = s1 ? q3y : w.q1y;
     w.a2 = s2 ? id3 : w.a2;  w.q2x = s2 ? q3x : w.q2x;  w.q2y = s2 ? q3y : w.q2y;
@@ -758,13 +784,31 @@ __device__ __forceinline__ bool walk_on(const Ray& s, int32_t max_steps) {
     return go;
 }
 
+// The walk of a set-up ray until it stops, in the plain float32 form.  With
+// STEPS false s.steps ends at 0: a per-lane step count costs a vector
+// instruction per step, and it is only written when the caller asks for it.
+template <bool TMAX, int LAYOUT, bool STEPS>
+__device__ __forceinline__ void walk_ray(const Mem& M, Ray& s, int32_t max_steps) {
+    Prec pc{0.0f, 0.0f, 0.0f, 0.0f, 0};
+    if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);   // the LINK form of walk_step
+    while (walk_on<TMAX>(s, max_steps)) {
+        walk_step<TMAX, LAYOUT, false, true>(M, s.f, s.g, s.w, pc);
+        ++s.steps;
+    }
+    if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
+    if (!STEPS) s.steps = 0;
+}
+
 // Result of a walk that stopped; the hit's t and barycentric weights come from
 // the Moller-Trumbore form in float64 with the triangle's vertices in ascending
 // caller-id order, so the weights are those of its 2nd and 3rd vertex.
 template <bool TMAX>
 __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, const Ray& s,
                            int32_t n64 = 0) {
-    const uint32_t nx = s.w.next;
+    // tested afresh here: reusing the walk loop's own test of the field would
+    // carry its outcome through every step in scalar registers
+    uint32_t nx = s.w.next;
+    keep(nx);
     if (!(nx & 0x80000000u)) {
         // tmax early-out, else the step cap
         const bool beyond = TMAX && (fminf(s.w.e0, fminf(s.w.e1, s.w.e2)) > s.tmax);
@@ -829,7 +873,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t 
     return (b - r) + (r % X) * G + r / X;
 }
 
-template <bool TMAX, int LAYOUT, bool PREC>
+template <bool TMAX, int LAYOUT, bool PREC, bool STEPS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 3 : 8)))
 k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds, kn.xcd_blocks)) * blockDim.x + threadIdx.x;
@@ -840,11 +884,7 @@ k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     Ray s;
     if (!PREC) {
         if (!setup_ray<TMAX, LAYOUT, false>(m, M, r, i, s, 0.0f)) return;
-        Prec pc{0.0f, 0.0f, 0.0f, 0.0f, 0};
-        while (walk_on<TMAX>(s, r.max_steps)) {
-            walk_step<TMAX, LAYOUT, false>(M, s.f, s.g, s.w, pc);
-            ++s.steps;
-        }
+        walk_ray<TMAX, LAYOUT, STEPS>(M, s, r.max_steps);
         finish_ray<TMAX>(m, M, r, i, s);
         return;
     }
@@ -936,7 +976,7 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
 // Batched launch: block b belongs to the job whose block range holds it (a
 // binary search that every lane of the block takes alike, so the job's
 // descriptors are read with scalar loads); the rest is the walk of k_trace.
-template <int LAYOUT>
+template <int LAYOUT, bool STEPS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs, uint32_t xcds) {
     const int64_t b = xcd_block(blockIdx.x, gridDim.x, xcds, 0u);
@@ -954,11 +994,7 @@ k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs, uint32_t xcds) {
     const Mem M = make_mem<LAYOUT>(m);
     Ray s;
     if (!setup_ray<true, LAYOUT, false>(m, M, r, i, s, 0.0f)) return;
-    Prec pc{0.0f, 0.0f, 0.0f, 0.0f, 0};
-    while (walk_on<true>(s, r.max_steps)) {
-        walk_step<true, LAYOUT, false>(M, s.f, s.g, s.w, pc);
-        ++s.steps;
-    }
+    walk_ray<true, LAYOUT, STEPS>(M, s, r.max_steps);
     finish_ray<true>(m, M, r, i, s, 0);
 }
 
@@ -991,11 +1027,14 @@ void launch_trace_t(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipS
         hipLaunchKernelGGL((k_trace_persistent<TMAX, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s,
                            m, r, refill);
     } else if (c.eps > 0.0f) {
-        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, true>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m,
-                           r, uint32_t(std::max(1, c.xcds)), Knobs{c.eps, uint32_t(c.xcd_blocks)});
+        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, true, true>), dim3(unsigned(simple_grid)), dim3(block), 0,
+                           s, m, r, uint32_t(std::max(1, c.xcds)), Knobs{c.eps, uint32_t(c.xcd_blocks)});
+    } else if (r.steps) {
+        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, false, true>), dim3(unsigned(simple_grid)), dim3(block), 0,
+                           s, m, r, uint32_t(std::max(1, c.xcds)), Knobs{0.0f, uint32_t(c.xcd_blocks)});
     } else {
-        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, false>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m,
-                           r, uint32_t(std::max(1, c.xcds)), Knobs{0.0f, uint32_t(c.xcd_blocks)});
+        hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, false, false>), dim3(unsigned(simple_grid)), dim3(block), 0,
+                           s, m, r, uint32_t(std::max(1, c.xcds)), Knobs{0.0f, uint32_t(c.xcd_blocks)});
     }
 }
 
@@ -1016,17 +1055,23 @@ hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, 
     return hipGetLastError();
 }
 
+template <int LAYOUT>
+void launch_trace_batch_t(const Job* d_jobs, int32_t n_jobs, dim3 g, dim3 b, uint32_t X, bool steps,
+                          hipStream_t s) {
+    if (steps)
+        hipLaunchKernelGGL((k_trace_batch<LAYOUT, true>), g, b, 0, s, d_jobs, n_jobs, X);
+    else
+        hipLaunchKernelGGL((k_trace_batch<LAYOUT, false>), g, b, 0, s, d_jobs, n_jobs, X);
+}
+
 hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_blocks, int32_t block,
-                              int32_t layout, int32_t xcds, hipStream_t s) {
+                              int32_t layout, int32_t xcds, bool steps, hipStream_t s) {
     const uint32_t X = uint32_t(std::max(1, xcds));
     if (total_blocks <= 0 || n_jobs <= 0) return hipSuccess;
     const dim3 g{unsigned(total_blocks)}, b{unsigned(block)};
-    if (layout == kTet16)
-        hipLaunchKernelGGL(k_trace_batch<kTet16>, g, b, 0, s, d_jobs, n_jobs, X);
-    else if (layout == kTet32N)
-        hipLaunchKernelGGL(k_trace_batch<kTet32N>, g, b, 0, s, d_jobs, n_jobs, X);
-    else
-        hipLaunchKernelGGL(k_trace_batch<kTet20>, g, b, 0, s, d_jobs, n_jobs, X);
+    if (layout == kTet16) launch_trace_batch_t<kTet16>(d_jobs, n_jobs, g, b, X, steps, s);
+    else if (layout == kTet32N) launch_trace_batch_t<kTet32N>(d_jobs, n_jobs, g, b, X, steps, s);
+    else launch_trace_batch_t<kTet20>(d_jobs, n_jobs, g, b, X, steps, s);
     return hipGetLastError();
 }
 
