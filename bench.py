@@ -41,6 +41,9 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 ALG_OPS_STEP = {"tet20": 30, "tet16": 38, "tet32n": 31}
 ALG_OPS_TMAX = 7
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_trace_ao_rays_12.6M_tets_hbm_traffic.md")
+L1_SUMMARY = os.path.join(ROOT, "profiles", "l1_line_rate_probe.md")
+CLOCK_HZ = 2.4e9
+N_CUS = 256
 # algorithmic bytes of one walk step: the fields the step needs, whatever the layout --
 # the xor field (4 B), one neighbour field (4 B) and the new point (12 B)
 STEP_BYTES = 20
@@ -53,10 +56,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper", choices=["paper", "tiny", "batch64", "serve", "ablate"],
+    ap.add_argument("--workload", default="paper",
+                    choices=["paper", "tiny", "batch64", "serve", "ablate", "l1probe"],
                     help="batch64: 64 uneven meshes in one batched launch; serve: Poisson request "
                          "stream over 16 resident meshes; ablate: record layouts x curve orders and "
-                         "camera distances on the 12.6M-tet scene (each prints its own line)")
+                         "camera distances on the 12.6M-tet scene; l1probe: the L1 cache-line access "
+                         "rate for 16-byte lane loads (each prints its own line)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="serve: seconds per offered rate")
     ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9",
                     help="serve: offered rates as fractions of the measured capacity")
@@ -115,6 +120,8 @@ def main():
         return bench_serve(args, tetrt, dev, log)
     if args.workload == "ablate":
         return bench_ablate(args, tetrt, dev, log)
+    if args.workload == "l1probe":
+        return bench_l1probe(args, tetrt, dev, log)
 
     t0 = time.time()
     m, eye, W, H = workload(args.workload)
@@ -225,7 +232,15 @@ def main():
     dom_ms, dom_bytes, dom_ops = kern[dom]
     achieved = dom_ops / (dom_ms * 1e-3) / 1e12
     alg_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args) if dom == "ao" else None
+    traffic, l1_acc, l2_req = measured_counters(args) if dom == "ao" else (None, None, None)
+    l1_peak, fill_peak = l1_rates()
+    mem = None
+    if l1_acc and l2_req and l1_peak:
+        cyc = dom_ms * 1e-3 * CLOCK_HZ * N_CUS   # CU-cycles of one launch
+        mem = {"l1_lookups_per_cu_cycle": round(l1_acc / cyc, 3), "l1_lookup_peak": l1_peak,
+               "l1_frac": round(l1_acc / cyc / l1_peak, 4),
+               "l2_fills_per_cu_cycle": round(l2_req / cyc, 3), "l2_fill_peak": fill_peak,
+               "l2_fill_frac": round(l2_req / cyc / fill_peak, 4)}
 
     line = {
         "metric": "closest-hit Mrays/s at 12.6M tets",
@@ -251,7 +266,9 @@ def main():
             "ray_binning": {0: "auto (AO rays)", 1: "off", 2: "on"}[args.sort], "eye": list(eye),
         },
         "roofline": {
-            # the walk is bound by VALU issue (counters: 92-100% busy), not by HBM
+            # VALU issue against the vector ALU peak.  "memory_pipeline": the same launch's
+            # L1 lookups and L1 fills from L2 per CU-cycle (committed counters) against the
+            # rates the calibration kernel sustains; the walk keeps all three near 60-70%
             "bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TOPS, 2),
             "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
             "kernel": "k_trace (%s rays)" % dom, "kernel_ms": round(float(dom_ms), 4),
@@ -260,6 +277,7 @@ def main():
             "hbm_frac_algorithmic": round(alg_gbs / HBM_PEAK_GBS, 4),
             "hbm_frac_measured": (round(traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                                   if traffic else None),
+            "memory_pipeline": mem,
         },
         "detail": {
             "primary_ms": round(float(ms_p.mean()), 4), "ao_ms": round(float(ms_a.mean()), 4),
@@ -298,27 +316,100 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(args):
-    """HBM bytes per launch of the AO walk, from the committed rocprofv3 counter
-    summary (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scaled by a device copy), or
-    None when the summary was taken on other kernel sources or another setup."""
-    if args.layout != "tet16" or args.sfc != "hilbert" or args.sort != 0 or args.block != 256:
-        return None
+def summary_values(path, keys):
+    """`key = value` lines of a committed counter summary."""
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(path).read()
     except OSError:
-        return None
+        return {}
     vals = {}
     for line in text.splitlines():
-        if "=" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
-            k, v = line.strip().strip("`").split("=", 1)
+        line = line.strip().strip("`")
+        if "=" in line and line.startswith(keys):
+            k, v = line.split("=", 1)
             vals[k.strip()] = v.strip().strip("`")
+    return vals
+
+
+def measured_counters(args):
+    """HBM bytes, L1 lookups and L1 fills from L2 per launch of the AO walk, from
+    the committed rocprofv3 counter summary (HBM: FETCH_SIZE x 2.0 + WRITE_SIZE x
+    1.0, scaled by a device copy; TCP_TOTAL_CACHE_ACCESSES; TCP_TCC_READ_REQ), or
+    None for each when the summary was taken on other kernel sources or another
+    setup."""
+    keys = ("traffic_bytes_per_launch", "l1_accesses_per_launch", "l2_requests_per_launch")
+    if args.layout != "tet16" or args.sfc != "hilbert" or args.sort != 0 or args.block != 256:
+        return (None,) * len(keys)
+    vals = summary_values(TRAFFIC_SUMMARY, keys + ("kernel_source_sha256",))
     if vals.get("kernel_source_sha256") != kernel_source_hash():
-        return None
+        return (None,) * len(keys)
+    out = []
+    for k in keys:
+        try:
+            out.append(int(vals[k]))
+        except (KeyError, ValueError):
+            out.append(None)
+    return tuple(out)
+
+
+def l1_rates():
+    """The memory pipeline's per-CU rates for 16-byte lane loads, from the
+    committed calibration summary: L1 lookups per cycle (lanes on distinct lines
+    spread over the line's offsets, all hits) and L1 fills from L2 per cycle
+    (all misses); (None, None) if absent."""
+    vals = summary_values(L1_SUMMARY, ("l1_lookups_per_cu_cycle", "l2_fills_per_cu_cycle"))
     try:
-        return int(vals["traffic_bytes_per_launch"])
+        return float(vals["l1_lookups_per_cu_cycle"]), float(vals["l2_fills_per_cu_cycle"])
     except (KeyError, ValueError):
-        return None
+        return None, None
+
+
+def bench_l1probe(args, tetrt, dev, log):
+    """The L1's line-lookup rate for wave loads of 16 bytes per lane, by address
+    spread: random 128-byte lines (each lane its own line) in L1-resident,
+    L2-resident and HBM-sized sets, and 8 lanes or a whole wave per line."""
+    import torch
+    blocks, iters = 2048, 2048   # 8 waves per SIMD on 256 CUs, 2048 loads per lane
+    buf = torch.ones(128 << 20, dtype=torch.uint8, device=dev)
+    out = torch.empty(blocks * 256 * 4, dtype=torch.int32, device=dev)
+    cases = [("random", 128, 128, "random 128-B lines, 16 KiB set"),
+             ("random", 1 << 14, 128, "random 128-B lines, 2 MiB set"),
+             ("random", 1 << 20, 128, "random 128-B lines, 128 MiB set"),
+             ("random", 256, 64, "random 64-B units, 16 KiB set"),
+             ("random", 1 << 10, 16, "random 16-B units, 16 KiB set"),
+             ("random", 1 << 12, 16, "random 16-B units, 64 KiB set"),
+             ("random", 1 << 14, 16, "random 16-B units, 256 KiB set"),
+             ("random", 1 << 17, 16, "random 16-B units, 2 MiB set"),
+             ("8_lanes", 128, 128, "8 lanes per 128-B line, 16 KiB set"),
+             ("one_line", 128, 128, "one 128-B line per wave load, 16 KiB set")]
+    st = torch.cuda.current_stream()
+    rows = []
+    for mode, units, ub, what in cases:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for rep in range(args.warmup + args.steps):
+            a.record(st)
+            tetrt.tetrt_probe_l1(buf, mode, ub, units, blocks, iters, out, st)
+            b.record(st)
+            b.synchronize()
+            if rep >= args.warmup:
+                ms.append(a.elapsed_time(b))
+        t = sorted(ms)[len(ms) // 2]
+        wave_loads = blocks * 4 * iters
+        cycles = t * 1e-3 * CLOCK_HZ
+        lines_per_load = {"random": units * (1 - (1 - 1 / units) ** 64) if ub == 128 else None,
+                          "8_lanes": 8, "one_line": 1}[mode]
+        row = {"case": what, "ms": round(t, 4),
+               "lane_loads_per_cu_cycle": round(wave_loads * 64 / N_CUS / cycles, 3),
+               "wave_loads_per_cu_cycle": round(wave_loads / N_CUS / cycles, 4)}
+        if lines_per_load:
+            row["expected_lines_per_wave_load"] = round(lines_per_load, 2)
+            row["lines_per_cu_cycle"] = round(wave_loads * lines_per_load / N_CUS / cycles, 3)
+        rows.append(row)
+        log(json.dumps(row))
+    print(json.dumps({"metric": "L1 cache-line lookups per CU per cycle, 16-byte lane loads",
+                      "cases": rows, "config": {"blocks": blocks, "block": 256, "iters": iters,
+                                                "clock_ghz": CLOCK_HZ / 1e9, "cus": N_CUS}}), flush=True)
 
 
 def bench_batch(args, tetrt, dev, log):

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtetrt.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("api.cpp", "batch.cpp", "server.cpp", "pack.cpp", "walk.hip", "sort.hip", "serve.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("api.cpp", "batch.cpp", "server.cpp", "pack.cpp", "walk.hip", "sort.hip", "serve.hip", "probe.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("pack.h", "device.h", "handle.h")] + [
     os.path.join(ROOT, "include", "tetrt.h")]
 

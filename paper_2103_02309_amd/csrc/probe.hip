@@ -1,0 +1,59 @@
+// Calibration kernel for the benchmark: the rate at which a CU's vector L1
+// serves wave loads whose lanes each read 16 bytes, for a chosen spread of the
+// lanes' addresses over cache lines.
+//
+// The walk reads, per ray and step, one 16-byte record and one 12-byte point at
+// addresses that differ from lane to lane; a wave's load then touches up to 64
+// cache lines.  The L1 looks lines up at a fixed rate per cycle, so that rate,
+// not the bytes moved, is what such loads are limited by.  This kernel
+// measures it: every lane of every wave issues `iters` independent 16-byte
+// loads whose addresses follow `mode`, and the caller times the launch.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "handle.h"
+#include "tetrt.h"
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_probe_l1(const uint4* __restrict__ buf, uint32_t units,
+                                                  uint32_t unit_u4, int32_t mode, int32_t iters,
+                                                  uint4* __restrict__ out) {
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t x = g * 2654435761u + 12345u;   // per-lane linear congruential sequence
+    uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+    for (int32_t k = 0; k < iters; ++k) {
+        x = x * 1664525u + 1013904223u;
+        uint32_t u;
+        if (mode == TM_PROBE_RANDOM) u = (x >> 8) & (units - 1u);
+        else if (mode == TM_PROBE_8_LANES) u = ((uint32_t(k) * 64u + lane) >> 3) & (units - 1u);
+        else u = uint32_t(k) & (units - 1u);
+        const uint4 v = buf[size_t(u) * unit_u4];
+        acc.x += v.x; acc.y ^= v.y; acc.z += v.z; acc.w ^= v.w;
+    }
+    out[g] = acc;
+}
+
+}  // namespace
+
+extern "C" int tetrt_probe_l1(const void* d_buf, uint64_t buf_bytes, int32_t mode, uint32_t unit_bytes,
+                              uint32_t units, int32_t blocks, int32_t iters, void* d_out, void* hip_stream) {
+    tetrt::clear_error();
+    if (mode != TM_PROBE_RANDOM && mode != TM_PROBE_8_LANES && mode != TM_PROBE_ONE_LINE)
+        return tetrt::fail(TM_ERR_ARG, "tetrt_probe_l1: unknown mode %d", mode);
+    if (unit_bytes < 16 || unit_bytes % 16 || units == 0 || (units & (units - 1u)))
+        return tetrt::fail(TM_ERR_ARG, "tetrt_probe_l1: unit_bytes must be a multiple of 16, units a power of 2");
+    if (uint64_t(units) * unit_bytes > buf_bytes)
+        return tetrt::fail(TM_ERR_ARG, "tetrt_probe_l1: units * unit_bytes exceeds the buffer");
+    if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
+        return tetrt::fail(TM_ERR_ARG, "tetrt_probe_l1: blocks and iters must be in [1, 2^20]");
+    if (!d_buf || !d_out) return tetrt::fail(TM_ERR_ARG, "tetrt_probe_l1: NULL buffer");
+    hipLaunchKernelGGL(k_probe_l1, dim3(unsigned(blocks)), dim3(256), 0, hipStream_t(hip_stream),
+                       static_cast<const uint4*>(d_buf), units, unit_bytes / 16u, mode, iters,
+                       static_cast<uint4*>(d_out));
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TM_OK : tetrt::hip_fail(e, "tetrt_probe_l1: launch");
+}

@@ -151,3 +151,22 @@ def test_server_argument_errors(tetrt):
     assert lib.tm_server_pending(None, None, None, None) == -1
     assert lib.tm_request_rays(None, None, 0, None, None, None, None, None, None, None) == -1
     assert lib.tm_server_free(None) == 0
+
+
+def test_probe_l1_argument_errors(tetrt):
+    """The calibration kernel's entry point rejects bad shapes before any launch
+    (the pointers below are never dereferenced)."""
+    L = tetrt.binding._load()
+    buf, out = C.c_void_p(4096), C.c_void_p(8192)
+    bad = [
+        (buf, 1 << 20, 7, 128, 128, 16, 16, out),        # unknown mode
+        (buf, 1 << 20, 0, 24, 128, 16, 16, out),         # unit not a multiple of 16
+        (buf, 1 << 20, 0, 128, 96, 16, 16, out),         # units not a power of two
+        (buf, 1 << 10, 0, 128, 128, 16, 16, out),        # set larger than the buffer
+        (buf, 1 << 20, 0, 128, 128, 0, 16, out),         # no blocks
+        (buf, 1 << 20, 0, 128, 128, 16, 1 << 21, out),   # too many iterations
+        (None, 1 << 20, 0, 128, 128, 16, 16, out),       # NULL buffer
+    ]
+    for a in bad:
+        assert L.tetrt_probe_l1(*a, None) == -1, a   # TM_ERR_ARG
+        assert "tetrt_probe_l1" in tetrt.tm_last_error()
