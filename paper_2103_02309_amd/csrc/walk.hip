@@ -375,11 +375,15 @@ __device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, f
 // instead of the field itself, before and after the step.  The step then
 // updates both in place (w.cur ^= NX[a] ^ NX[b], w.next ^= w.cur) rather than
 // rotating previous / current / next through registers.
-template <bool DEPTH, int LAYOUT, bool PREC, bool LINK = false>
-__device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const Depth& g, Walk& w,
-                                          Prec& pc) {
+// R is the record of w.next.  PIPE: as soon as the step knows the next tet,
+// it loads that tet's record into *ahead, so the load is in flight while the
+// step finishes; for a lane whose walk ends there the index is a face flag or
+// the boundary mark, beyond the record count, and the buffer bound makes the
+// load return zeros without touching memory.
+template <bool DEPTH, int LAYOUT, bool PREC, bool LINK = false, bool PIPE = false>
+__device__ __forceinline__ void walk_step_rec(const Mem& M, const Frame& f, const Depth& g, Walk& w,
+                                              Prec& pc, const Rec& R, Rec* ahead) {
     const uint32_t tet = w.next;
-    const Rec R = load_rec<LAYOUT>(M, tet);
     const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ (LAYOUT == kTet32N ? w.vxn : R.vx);
     const float4 P = load_pt(M, uint32_t(id3));
     float q3x, q3y;
@@ -430,6 +434,7 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
         w.cur = int32_t(tet);
     }
     if (LAYOUT == kTet32N) w.vxn = int32_t(pick4b(R.w0, R.w1, R.w2, R.w3, rlo, rhi));
+    if (PIPE) *ahead = load_rec<LAYOUT>(M, w.next);
     w.a0 = s0 ? id3 : w.a0;  w.q0x = s0 ? q3x : w.q0x;  w.q0y = s0 ? q3y : w.q0y;
     w.a1 = s1 ? id3 : w.a1;  w.q1x = s1 ? q3x : w.q1x;  w.q1y = s1 ? q3y : w.q1y;
     w.a2 = s2 ? id3 : w.a2;  w.q2x = s2 ? q3x : w.q2x;  w.q2y = s2 ? q3y : w.q2y;
@@ -439,6 +444,13 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
         w.e1 = s1 ? e3 : w.e1;
         w.e2 = s2 ? e3 : w.e2;
     }
+}
+
+template <bool DEPTH, int LAYOUT, bool PREC, bool LINK = false>
+__device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const Depth& g, Walk& w,
+                                          Prec& pc) {
+    const Rec R = load_rec<LAYOUT>(M, w.next);
+    walk_step_rec<DEPTH, LAYOUT, PREC, LINK, false>(M, f, g, w, pc, R, nullptr);
 }
 
 // Exit face of tet `tet` (vertex ids v[0..3]) for the line X + s*D: the face
@@ -791,8 +803,9 @@ template <bool TMAX, int LAYOUT, bool STEPS>
 __device__ __forceinline__ void walk_ray(const Mem& M, Ray& s, int32_t max_steps) {
     Prec pc{0.0f, 0.0f, 0.0f, 0.0f, 0};
     if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);   // the LINK form of walk_step
+    Rec R = load_rec<LAYOUT>(M, s.w.next);
     while (walk_on<TMAX>(s, max_steps)) {
-        walk_step<TMAX, LAYOUT, false, true>(M, s.f, s.g, s.w, pc);
+        walk_step_rec<TMAX, LAYOUT, false, true, true>(M, s.f, s.g, s.w, pc, R, &R);
         ++s.steps;
     }
     if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
