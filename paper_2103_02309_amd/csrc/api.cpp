@@ -114,7 +114,8 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     if (n_points < 4 || n_points >= int64_t(0x80000000LL))
         return fail(TM_ERR_ARG, "tetmesh_upload: n_points = %lld out of range [4, 2^31)",
                     (long long)n_points);
-    // the kernels address records and points with 32-bit byte offsets
+    // records and points below 4 GiB each: the sizes the packer's index arithmetic
+    // is written for
     {
         const int64_t rb = (opts && opts->layout == TM_LAYOUT_TET32N) ? 32 : 20;
         if (n_tets * rb > int64_t(0xFFFFFFFFLL) || n_points * 16 > int64_t(0xFFFFFFFFLL))
