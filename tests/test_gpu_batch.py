@@ -114,6 +114,23 @@ def test_batch_matches_single(tetrt, scenes, uploaded, block):
     b.free()
 
 
+def test_batch_without_step_counts(tetrt, scenes, uploaded):
+    """Jobs without step-count or tet-id outputs take the batch kernel that keeps
+    no per-ray counts; results equal the counting path bit for bit."""
+    jobs = _jobs(tetrt, scenes, uploaded)
+    for j in jobs:
+        n = int(j["orig"].shape[0])
+        j["out"] = tetrt.outputs(n, "cuda:0", False, False)
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))
+    b.set(jobs)
+    b.launch()
+    for k, j in enumerate(jobs):
+        got, ref = _host(j["out"]), _single(j)
+        for key in ("tri", "t", "bary"):
+            assert np.array_equal(got[key], ref[key], equal_nan=True), (k, key)
+    b.free()
+
+
 def test_batch_oracle(tetrt, scenes, uploaded):
     jobs = [j for j in _jobs(tetrt, scenes, uploaded, empty_at=()) if j["orig"].shape[0] > 0]
     b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))

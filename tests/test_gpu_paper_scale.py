@@ -63,6 +63,17 @@ def test_primary_all_rays_properties(paper):
     assert 0.3 < (got["tri"] >= 0).mean() < 0.95
 
 
+def test_primary_benchmark_kernel_identical(paper):
+    """The benchmark times the walk without per-ray step counts and tet ids (a
+    kernel of its own): on all 2,073,600 rays it gives bit for bit the results
+    of the counting kernel that the oracle comparisons below check."""
+    m, mesh, om, o, d, got = paper
+    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), block=256)
+    torch.cuda.synchronize()
+    for k, v in res.items():
+        assert np.array_equal(v.cpu().numpy(), got[k], equal_nan=True), k
+
+
 def test_primary_sampled_vs_oracle(paper):
     m, mesh, om, o, d, got = paper
     idx = np.sort(np.random.default_rng(12).choice(o.shape[0], 20000, replace=False))
@@ -97,6 +108,12 @@ def test_ao_sampled_vs_oracle(paper):
     rep = compare(m.points, om.tri_verts, ao, ad, ref, g, tmax=atm)
     assert rep["ok"], rep
     _check_properties(m, mesh, ao, ad, g, atm)
+    # the benchmark's kernel (no step counts or tet ids) gives the same results
+    res = mesh.trace(torch.from_numpy(ao).cuda(), torch.from_numpy(ad).cuda(),
+                     tmax=torch.from_numpy(atm).cuda(), start_face=torch.from_numpy(sf).cuda(), sort=2)
+    torch.cuda.synchronize()
+    for k, v in res.items():
+        assert np.array_equal(v.cpu().numpy(), g[k], equal_nan=True), k
 
 
 def test_ao_from_device_hits_properties(paper):

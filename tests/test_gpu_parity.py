@@ -64,6 +64,29 @@ def test_tiny_primary(tiny, kw):
     assert (got["steps"] == ref["steps"]).mean() > 0.999
 
 
+def test_tiny_without_step_counts(tiny):
+    """Without per-ray step counts (the kernel the benchmark times) every layout
+    matches the oracle and gives bit for bit what the counting kernel gives,
+    primary and AO rays."""
+    m, om, mesh = tiny
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 64, 64, 60.0)
+    ref = om.trace(o, d)
+    plain = _host(mesh.trace(_dev(o), _dev(d)))
+    counted = _host(mesh.trace(_dev(o), _dev(d), want_steps=True))
+    rep = compare(m.points, om.tri_verts, o, d, ref, plain)
+    assert rep["ok"], rep
+    for k in plain:
+        assert np.array_equal(plain[k], counted[k], equal_nan=True), k
+    ao, ad, atm, sf = _ao_from(m, om, o, d, ref)
+    A = [_dev(x) for x in (ao, ad, atm, sf)]
+    plain = _host(mesh.trace(A[0], A[1], tmax=A[2], start_face=A[3]))
+    counted = _host(mesh.trace(A[0], A[1], tmax=A[2], start_face=A[3], want_steps=True))
+    rep = compare(m.points, om.tri_verts, ao, ad, om.trace(ao, ad, atm, start_face=sf), plain, tmax=atm)
+    assert rep["ok"], rep
+    for k in plain:
+        assert np.array_equal(plain[k], counted[k], equal_nan=True), k
+
+
 @pytest.mark.parametrize("kw", KERNELS)
 def test_tiny_ao(tiny, kw):
     m, om, mesh = tiny
