@@ -29,22 +29,24 @@
 //
 // Memory (paper, Sec. "Tetrahedral Mesh Representation"):
 //   Tet20  20 packed bytes {VX, N0, N1, N2, N3}, read as one 16-byte and one
-//          4-byte buffer load issued together at the top of a step;
+//          4-byte load;
 //   Tet16  16 bytes {VX, NX0, NX1, NX2} with NX_j = N_j ^ N_3, one aligned
 //          16-byte load; the neighbour across the exit face is the field of the
 //          entry face (known: it refers back to the previous tet) xor NX of the
 //          entry vertex's rank xor NX of the exit vertex's rank (NX_3 = 0),
 //          Algorithms 6-7.
-// With these the point is one 16-byte load after the record, so a step is
-// two dependent round trips (record, then point).
+//   With these the point is one 12-byte load after the record, so a step is
+//   two dependent round trips (record, then point).  The next record's load is
+//   issued inside the step, as soon as the exit face is known.
 //   Tet32N 32 bytes {N0..N3, W0..W3}: the neighbour fields and each
 //          neighbour's xor-sum.  The xor-sum of the tet being entered comes
 //          with the previous record, so the record and the point of a step are
-//          loaded together: one round trip per step, for twice the bytes of
-//          Tet16.  Not one of the paper's layouts: the paper's xor idea moved
-//          one step ahead, because on gfx950 the walk is bound by the latency of
-//          dependent loads rather than by bytes.  Buffer loads return zero beyond the array instead of
-// faulting, and the step is branch-free: the loop test is its only branch.
+//          loaded together: one round trip per step, for twice the bytes and
+//          one more L1 lookup per lane than Tet16.  Not one of the paper's
+//          layouts: the paper's xor idea moved one step ahead.
+// Records and points are read by id through structured buffer descriptors: an
+// index past the array reads zero instead of faulting.  The step is
+// branch-free: the loop test is its only branch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -862,7 +864,7 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
 // One lane per ray: set-up, walk, result.
 // 8 waves per SIMD (at most 64 VGPRs): the walk is latency-bound, so occupancy
 // is what hides the memory round trips.  The precision variant carries float64
-// code and settles for 4 waves rather than spilling.
+// code and settles for 3 waves rather than spilling.
 // The dispatcher deals blocks to the XCDs round-robin (block b runs on XCD
 // b mod X), and each XCD has an L2 of its own.  Renumbering blocks so that
 // consecutive ones share an XCD keeps neighbouring rays -- which visit the same
