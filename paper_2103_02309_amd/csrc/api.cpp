@@ -259,9 +259,8 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     // the dispatcher's round-robin placement, which balances walks of uneven length
     c.xcds = o.xcds ? o.xcds : ((binned || o.order) ? tetrt::xcd_count(m->cus) : 1);
     c.xcd_blocks = o.xcd_blocks;
-    // persistent lanes pay off once every lane gets several rays
-    const int64_t lanes = int64_t(c.cus) * 4 * 64 * c.waves_per_simd;
-    (void)lanes;
+    // automatic: one lane per ray (the persistent-lane kernel is slower on every
+    // measured workload and runs only when asked for)
     c.kernel = o.kernel ? o.kernel : 1;
     c.eps = o.eps;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
