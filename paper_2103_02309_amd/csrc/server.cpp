@@ -230,10 +230,20 @@ int step(tm_server_s* s, hipStream_t stream, int64_t* launched) {
         rays += q.n;
     }
     if (jobs.empty()) return TM_OK;
+    // on a failed launch the step's requests go back to pending, to be launched
+    // again by a later step
+    auto undo = [&](int rc) {
+        for (const auto& it : sl.items) {
+            auto r = s->reqs.find(it.first);
+            if (r != s->reqs.end()) r->second.st = r->second.st == St::Flight0 ? St::Pending0 : St::Pending1;
+        }
+        sl.items.clear();
+        return rc;
+    };
     std::memcpy(sl.h_gen, gen.data(), gen.size() * sizeof(tetrt::GenEntry));
     e = hipMemcpyAsync(sl.d_gen, sl.h_gen, gen.size() * sizeof(tetrt::GenEntry), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = tetrt::launch_gen(sl.d_gen, int32_t(gen.size()), blocks, s->pool, stream);
-    if (e != hipSuccess) return hip_fail(e, "tm_server_step: ray generation");
+    if (e != hipSuccess) return undo(hip_fail(e, "tm_server_step: ray generation"));
     tm_trace_opts to;
     std::memset(&to, 0, sizeof to);
     to.block = s->o.block;
@@ -241,9 +251,9 @@ int step(tm_server_s* s, hipStream_t stream, int64_t* launched) {
     to.max_steps = s->o.max_steps;
     int rc = tm_batch_set(sl.batch, int32_t(jobs.size()), jobs.data(), &to, stream);
     if (rc == TM_OK) rc = tm_batch_launch(sl.batch, stream);
-    if (rc != TM_OK) return rc;
+    if (rc != TM_OK) return undo(rc);
     e = hipEventRecord(sl.done, stream);
-    if (e != hipSuccess) return hip_fail(e, "tm_server_step: event record");
+    if (e != hipSuccess) return undo(hip_fail(e, "tm_server_step: event record"));
     sl.busy = true;
     s->order.push_back(s->next_slot);
     s->next_slot = (s->next_slot + 1) % int(s->ring.size());
