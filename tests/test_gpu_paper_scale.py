@@ -22,8 +22,8 @@ def scene():
     return m, om, o, d
 
 
-# Tet16 is the benchmark's layout; Tet20 is the paper's GPU layout
-@pytest.fixture(scope="module", params=["tet16", "tet20"])
+# Tet16 is the benchmark's layout; Tet20 is the paper's GPU layout; Tet32N the one-round-trip variant
+@pytest.fixture(scope="module", params=["tet16", "tet20", "tet32n"])
 def paper(request, scene):
     import paper_2103_02309_amd as tetrt
     m, om, o, d = scene
