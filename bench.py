@@ -207,6 +207,7 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: %d bytes read, %d bytes written" % (nbytes, nbytes))
         del src, dst
+    copy_gbs = attainable_copy_gbs(torch, dev)
     torch.cuda.synchronize()
 
     K = args.steps
@@ -232,7 +233,7 @@ def main():
     dom_ms, dom_bytes, dom_ops = kern[dom]
     achieved = dom_ops / (dom_ms * 1e-3) / 1e12
     alg_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic, l1_acc, l2_req = measured_counters(args) if dom == "ao" else (None, None, None)
+    traffic, l1_acc, l2_req, l2_hit = measured_counters(args) if dom == "ao" else (None,) * 4
     l1_peak, fill_peak = l1_rates()
     mem = None
     if l1_acc and l2_req and l1_peak:
@@ -279,6 +280,8 @@ def main():
             "measured_gbs": round(traffic / (dom_ms * 1e-3) / 1e9, 1) if traffic else None,
             "measured_frac": (round(traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                               if traffic else None),
+            "hbm_copy_gbs": copy_gbs,
+            "l2_hit_rate": l2_hit,
             "alu": {"achieved": round(achieved, 2), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s",
                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "algorithmic_ops": dom_ops},
             "memory_pipeline": mem,
@@ -341,7 +344,7 @@ def measured_counters(args):
     1.0, scaled by a device copy; TCP_TOTAL_CACHE_ACCESSES; TCP_TCC_READ_REQ), or
     None for each when the summary was taken on other kernel sources or another
     setup."""
-    keys = ("traffic_bytes_per_launch", "l1_accesses_per_launch", "l2_requests_per_launch")
+    keys = ("traffic_bytes_per_launch", "l1_accesses_per_launch", "l2_requests_per_launch", "l2_hit_rate")
     if args.layout != "tet16" or args.sfc != "hilbert" or args.sort != 0 or args.block != 256:
         return (None,) * len(keys)
     vals = summary_values(TRAFFIC_SUMMARY, keys + ("kernel_source_sha256",))
@@ -350,10 +353,29 @@ def measured_counters(args):
     out = []
     for k in keys:
         try:
-            out.append(int(vals[k]))
+            out.append(float(vals[k]) if k == "l2_hit_rate" else int(vals[k]))
         except (KeyError, ValueError):
             out.append(None)
     return tuple(out)
+
+
+def attainable_copy_gbs(torch, dev, nbytes=1 << 30, reps=5):
+    """Device-to-device copy bandwidth on this GPU (bytes read + written per
+    second, median of `reps` 1 GiB copies): the HBM rate a streaming kernel
+    attains, beside the 8 TB/s peak."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    del src, dst
+    return round(2 * nbytes / (sorted(ms)[reps // 2] * 1e-3) / 1e9, 1)
 
 
 def l1_rates():
@@ -743,7 +765,20 @@ def cpu_baseline(m, o, d, ao, ad, atm, sf, parent, hit, stride, threads, log):
         threads, sel.shape[0], t1 - t0, sel_a.shape[0], t2 - t1))
     return {"value": round(n / (t2 - t0) / 1e6, 4), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
             "sample": "every %d-th primary ray (%d) + the AO rays of their hits (%d), %.1f s wall on %d "
-                      "threads" % (stride, sel.shape[0], sel_a.shape[0], t2 - t0, threads)}
+                      "threads" % (stride, sel.shape[0], sel_a.shape[0], t2 - t0, threads),
+            "cpu": cpu_model()}
+
+
+def cpu_model():
+    """The host CPU's model name, as /proc/cpuinfo gives it."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":
