@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--sort-dirq", type=int, default=0, help="direction bins per axis (0 = default)")
     ap.add_argument("--sort-cells", type=int, default=0, help="log2 origin cells per axis (0 = default)")
     ap.add_argument("--eye", default="", help="camera position x,y,z (default: the workload's)")
+    ap.add_argument("--eps", type=float, default=0.0,
+                    help="precision variant threshold for both passes (0 = plain float32 walk)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads for the CPU baseline (0 = the host's CPUs, at most 16)")
@@ -176,7 +178,7 @@ def main():
 
     # binning: the library's automatic rule (batches of at least 2^18 rays that carry
     # tmax), run as its own kernel so that the walk kernel is timed apart
-    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill)
+    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill, eps=args.eps)
     skw = dict(sort_chunk_log2=args.sort_chunk, sort_dirq=args.sort_dirq, sort_cells_log2=args.sort_cells)
     bin_p = args.sort == 2
     bin_a = args.sort == 2 or (args.sort == 0 and n_a >= (1 << 18))
@@ -265,6 +267,7 @@ def main():
             "layout": args.layout, "sfc": args.sfc, "block": args.block,
             "kernel": {0: "auto", 1: "one lane per ray", 2: "persistent lanes"}[args.kernel],
             "ray_binning": {0: "auto (AO rays)", 1: "off", 2: "on"}[args.sort], "eye": list(eye),
+            "precision_eps": args.eps,
         },
         "roofline": {
             # the walk reads memory: HBM roofline of the algorithmic bytes (20 B per step +
@@ -345,7 +348,8 @@ def measured_counters(args):
     None for each when the summary was taken on other kernel sources or another
     setup."""
     keys = ("traffic_bytes_per_launch", "l1_accesses_per_launch", "l2_requests_per_launch", "l2_hit_rate")
-    if args.layout != "tet16" or args.sfc != "hilbert" or args.sort != 0 or args.block != 256:
+    if (args.layout != "tet16" or args.sfc != "hilbert" or args.sort != 0 or args.block != 256 or args.eps > 0
+            or args.kernel not in (0, 1)):
         return (None,) * len(keys)
     vals = summary_values(TRAFFIC_SUMMARY, keys + ("kernel_source_sha256",))
     if vals.get("kernel_source_sha256") != kernel_source_hash():
