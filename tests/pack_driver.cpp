@@ -1,5 +1,5 @@
 // Host-only driver for the mesh packer, built with AddressSanitizer and
-// UndefinedBehaviorSanitizer by tests/test_pack_sanitized.py: packs a mesh read
+// UndefinedBehaviorSanitizer by tests/test_host_sanitized.py: packs a mesh read
 // from a binary file in every record layout and curve order, then runs the
 // validation on corrupted copies of it.  Prints one line per run.
 #include <cstdio>
