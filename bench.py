@@ -9,8 +9,9 @@ at (0.5, 0.5, 0.02) looking +z with a 60 degree horizontal field of view
 (tmax 0.1) from every primary hit.  The AO ray set is built once, before
 timing, from the library's own primary hits.
 
-One step = trace_closest on all primary rays (each locates its origin on the
-device) + trace_closest on all AO rays (each starts from its hit face).  Inputs
+One step = the camera located once on the device (tetmesh_locate) +
+trace_closest on all primary rays, started in that tet + binning of the AO rays
++ trace_closest on the AO rays (each starts from its hit face).  Inputs
 are resident in device memory when timing starts; the mesh upload is timed
 separately.  Kernel times come from HIP events on the launch stream.
 
@@ -79,6 +80,8 @@ def parse():
     ap.add_argument("--sort-dirq", type=int, default=0, help="direction bins per axis (0 = default)")
     ap.add_argument("--sort-cells", type=int, default=0, help="log2 origin cells per axis (0 = default)")
     ap.add_argument("--eye", default="", help="camera position x,y,z (default: the workload's)")
+    ap.add_argument("--locate", default="shared", choices=["shared", "per-ray"],
+                    help="primary rays: camera located once per pass (shared) or by every ray")
     ap.add_argument("--eps", type=float, default=0.0,
                     help="precision variant threshold for both passes (0 = plain float32 walk)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -140,9 +143,21 @@ def main():
     o, d, pix = pinhole_rays(eye, W, H, 60.0, tile=args.tile)
     po, pd = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
     n_p = o.shape[0]
+    # the pinhole's rays share one origin: it is located once per pass on the device
+    # (tetmesh_locate) and broadcast as every primary ray's start tet, as the paper
+    # locates the camera once; --locate per-ray has every ray locate it again
+    cam = torch.tensor([list(eye)], dtype=torch.float32, device=dev)
+    cam_tet = torch.empty(1, dtype=torch.int32, device=dev)
+    start_p = torch.empty(n_p, dtype=torch.int32, device=dev) if args.locate == "shared" else None
+
+    def locate_camera():
+        if start_p is not None:
+            tetrt.tetmesh_locate(mesh.handle, cam, cam_tet)
+            start_p.copy_(cam_tet.expand(n_p))
+        return start_p
 
     # set-up pass (untimed): primary hits -> AO rays, step counts for the byte model
-    res = mesh.trace(po, pd, want_steps=True)
+    res = mesh.trace(po, pd, start_tet=locate_camera(), want_steps=True)
     torch.cuda.synchronize()
     tri = res["tri"].cpu().numpy()
     tp = res["t"].cpu().numpy()
@@ -191,7 +206,7 @@ def main():
         if bin_p:
             mesh.bin_rays(po, pd, ord_p, **skw)
         rec(1)
-        mesh.trace_into(out_p, po, pd, order=ord_p, sort=1, **kw)
+        mesh.trace_into(out_p, po, pd, start_tet=locate_camera(), order=ord_p, sort=1, **kw)
         rec(2)
         if bin_a:
             mesh.bin_rays(ao_t, ad_t, ord_a, **skw)
@@ -268,6 +283,8 @@ def main():
             "kernel": {0: "auto", 1: "one lane per ray", 2: "persistent lanes"}[args.kernel],
             "ray_binning": {0: "auto (AO rays)", 1: "off", 2: "on"}[args.sort], "eye": list(eye),
             "precision_eps": args.eps,
+            "primary_start": ("camera located once per pass on the device, shared by every primary ray"
+                              if args.locate == "shared" else "every primary ray locates the camera"),
         },
         "roofline": {
             # the walk reads memory: HBM roofline of the algorithmic bytes (20 B per step +

@@ -72,6 +72,18 @@ def test_primary_benchmark_kernel_identical(paper):
     torch.cuda.synchronize()
     for k, v in res.items():
         assert np.array_equal(v.cpu().numpy(), got[k], equal_nan=True), k
+    # ... and with the camera located once on the device and shared as every ray's
+    # start tet, as the benchmark runs it
+    import paper_2103_02309_amd as tetrt
+    cam = torch.tensor([[0.5, 0.5, 0.02]], dtype=torch.float32, device="cuda:0")
+    cam_tet = torch.empty(1, dtype=torch.int32, device="cuda:0")
+    tetrt.tetmesh_locate(mesh.handle, cam, cam_tet)
+    start = cam_tet.expand(o.shape[0]).contiguous()
+    assert int(cam_tet.item()) == int(om.locate(o[:1])[0])
+    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), start_tet=start, block=256)
+    torch.cuda.synchronize()
+    for k, v in res.items():
+        assert np.array_equal(v.cpu().numpy(), got[k], equal_nan=True), k
 
 
 def test_primary_sampled_vs_oracle(paper):
