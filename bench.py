@@ -58,11 +58,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper",
-                    choices=["paper", "tiny", "batch64", "serve", "ablate", "l1probe"],
+                    choices=["paper", "tiny", "batch64", "serve", "ablate", "l1probe", "precision"],
                     help="batch64: 64 uneven meshes in one batched launch; serve: Poisson request "
                          "stream over 16 resident meshes; ablate: record layouts x curve orders and "
                          "camera distances on the 12.6M-tet scene; l1probe: the L1 cache-line access "
-                         "rate for 16-byte lane loads (each prints its own line)")
+                         "rate for 16-byte lane loads; precision: the float64 re-evaluation variant on "
+                         "2M stress rays, speed and agreement with the oracle (each prints its own line)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="serve: seconds per offered rate")
     ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9",
                     help="serve: offered rates as fractions of the measured capacity")
@@ -127,6 +128,8 @@ def main():
         return bench_ablate(args, tetrt, dev, log)
     if args.workload == "l1probe":
         return bench_l1probe(args, tetrt, dev, log)
+    if args.workload == "precision":
+        return bench_precision(args, tetrt, dev, log)
 
     t0 = time.time()
     m, eye, W, H = workload(args.workload)
@@ -409,6 +412,70 @@ def l1_rates():
         return float(vals["l1_lookups_per_cu_cycle"]), float(vals["l2_fills_per_cu_cycle"])
     except (KeyError, ValueError):
         return None, None
+
+
+def bench_precision(args, tetrt, dev, log):
+    """The precision variant on the stress set: 2,000,000 rays on the 16^3 scene
+    (10% aimed through mesh vertices, 10% along non-surface edges, 80% random),
+    for eps = 0 (plain float32 walk) and the sweep 1e-7 .. 1e-4: walk time and
+    Mrays/s (every ray locates its own origin), and per ray kind the share of rays
+    whose triangle differs from the FP64 oracle's, how many of those are not
+    explained by an edge/vertex tie, step caps and invalid results, and the share
+    of steps decided in float64."""
+    import numpy as np
+    import torch
+    import oracle
+    from oracle.compare import compare
+    from synth import config_mesh, precision_rays
+    m = config_mesh("tiny")
+    om = oracle.OracleMesh.from_kuhn(m)
+    n = 2_000_000
+    o, d, kind = precision_rays(m.points, m.tets, m.cflag, n=n, seed=4)
+    t0 = time.time()
+    threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+    from concurrent.futures import ThreadPoolExecutor
+    b = np.linspace(0, n, threads + 1).astype(np.int64)
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda k: om.trace(o[b[k]:b[k + 1]], d[b[k]:b[k + 1]]), range(threads)))
+    ref = {key: np.concatenate([p[key] for p in parts]) for key in parts[0]}
+    log("oracle: %d rays in %.1f s on %d threads" % (n, time.time() - t0, threads))
+    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=args.layout)
+    O, D = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+    out = tetrt.outputs(n, dev, want_steps=True)
+    out["fp64_steps"] = torch.empty(n, dtype=torch.int32, device=dev)
+    rows = []
+    for eps in (0.0, 1e-7, 1e-6, 1e-5, 1e-4):
+        kw = dict(eps=eps, max_steps=20000)
+        mesh.trace_into(out, O, D, **kw)   # warm-up, and the results checked below
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+        ms = []
+        for _ in range(max(3, args.steps // 4)):
+            a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            mesh.trace_into(out, O, D, **kw)
+            e.record()
+            e.synchronize()
+            ms.append(a.elapsed_time(e))
+        t = sorted(ms)[len(ms) // 2]
+        row = {"eps": eps, "ms": round(t, 4), "mrays_s": round(n / t / 1e3, 1),
+               "fp64_step_share": round(float(got["fp64_steps"].sum()) / max(1.0, float(got["steps"].clip(0).sum())), 6)}
+        for k, name in {0: "random", 1: "through vertices", 2: "along edges"}.items():
+            sel = kind == k
+            rep = compare(m.points, om.tri_verts, o[sel], d[sel], {x: v[sel] for x, v in ref.items()},
+                          {x: v[sel] for x, v in got.items()})
+            row[name] = {"rays": int(sel.sum()), "mismatch_rate": round(1.0 - rep["frac_identical"], 7),
+                         "unexplained": int(rep["n_unexplained"]),
+                         "step_caps": int((got["tri"][sel] == -2).sum()),
+                         "invalid": int((got["tri"][sel] == -3).sum())}
+        rows.append(row)
+        log(json.dumps(row))
+    mesh.free()
+    print(json.dumps({"metric": "precision variant on 2M stress rays (16^3 scene)", "unit": "Mrays/s",
+                      "dtype": "f32 walk, f64 re-evaluation", "data": "synthetic", "rows": rows,
+                      "config": {"workload": "kuhn16-sphere, 2M rays: 10% through vertices, 10% along "
+                                             "non-surface edges, 80% random", "layout": args.layout}}),
+          flush=True)
 
 
 def bench_l1probe(args, tetrt, dev, log):
