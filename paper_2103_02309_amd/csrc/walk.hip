@@ -189,10 +189,23 @@ struct Frame {
     float pox, poy;     // projected origin (Eq. 4)
 };
 
-// 2-D determinant with both products rounded before the subtraction, so that
-// det(a, b) == -det(b, a) exactly (no fused contraction).
+// 2-D determinant with both products rounded before the subtraction (no fused
+// multiply-add), so that det(a, b) == -det(b, a) exactly.
 __device__ __forceinline__ float det2(float ax, float ay, float bx, float by) {
-    return __fmul_rn(ax, by) - __fmul_rn(ay, bx);
+#pragma clang fp contract(off)
+    return ax * by - ay * bx;
+}
+
+// The sign tests of det2 as comparisons of the two rounded products: for
+// finite values the rounded difference is negative, or not, exactly when the
+// first product is below the second, or not.
+__device__ __forceinline__ bool det2_neg(float ax, float ay, float bx, float by) {
+#pragma clang fp contract(off)
+    return ax * by < ay * bx;
+}
+__device__ __forceinline__ bool det2_nonneg(float ax, float ay, float bx, float by) {
+#pragma clang fp contract(off)
+    return ax * by >= ay * bx;
 }
 
 // Eq. 1-2 for direction n (not necessarily unit).  Index names: i = smallest
@@ -392,17 +405,18 @@ __device__ __forceinline__ void walk_step_rec(const Mem& M, const Frame& f, cons
     project(f, P, q3x, q3y);
     // Algorithm 1 as lane masks: the exit face drops slot 1 when det(q3,q0) < 0 and
     // det(q3,q2) >= 0, slot 2 when det(q3,q0) >= 0 and det(q3,q1) < 0, else slot 0
-    const uint64_t N0 = lanes(det2(q3x, q3y, w.q0x, w.q0y) < 0.0f);
-    const uint64_t N1 = lanes(det2(q3x, q3y, w.q1x, w.q1y) < 0.0f);
-    const uint64_t P2 = lanes(det2(q3x, q3y, w.q2x, w.q2y) >= 0.0f);
+    const uint64_t N0 = lanes(det2_neg(q3x, q3y, w.q0x, w.q0y));
+    const uint64_t N1 = lanes(det2_neg(q3x, q3y, w.q1x, w.q1y));
+    const uint64_t P2 = lanes(det2_nonneg(q3x, q3y, w.q2x, w.q2y));
     uint64_t S1 = N0 & P2, S2 = N1 & ~N0;
     if (PREC) {
         int e = lane(S1) ? 1 : (lane(S2) ? 2 : 0);
         const float s3 = fabsf(q3x) + fabsf(q3y);
+        // evaluated in full (no short circuit: branches would cost more than the tests)
         const bool unsure =
-            fabsf(det2(q3x, q3y, w.q0x, w.q0y)) <= pc.eps * (s3 + fabsf(w.q0x) + fabsf(w.q0y)) ||
-            fabsf(det2(q3x, q3y, w.q1x, w.q1y)) <= pc.eps * (s3 + fabsf(w.q1x) + fabsf(w.q1y)) ||
-            fabsf(det2(q3x, q3y, w.q2x, w.q2y)) <= pc.eps * (s3 + fabsf(w.q2x) + fabsf(w.q2y));
+            (fabsf(det2(q3x, q3y, w.q0x, w.q0y)) <= pc.eps * (s3 + fabsf(w.q0x) + fabsf(w.q0y))) |
+            (fabsf(det2(q3x, q3y, w.q1x, w.q1y)) <= pc.eps * (s3 + fabsf(w.q1x) + fabsf(w.q1y))) |
+            (fabsf(det2(q3x, q3y, w.q2x, w.q2y)) <= pc.eps * (s3 + fabsf(w.q2x) + fabsf(w.q2y)));
         if (unsure) {
             e = exit_slot64(M, f, pc, w.a0, w.a1, w.a2, P);
             ++pc.n64;
