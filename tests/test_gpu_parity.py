@@ -323,3 +323,32 @@ def test_caller_order(tiny, tetrt):
     assert np.all(h["tri"][skipped] == -9)
     rest = np.setdiff1d(np.arange(30001), skipped)
     assert np.array_equal(h["tri"][rest], a["tri"][rest])
+
+
+def test_concurrent_streams_on_one_handle(tiny, tetrt):
+    """A handle is read-only after upload: traces enqueued on two streams at once
+    (unbinned primary rays on one, binned secondary rays with their own workspace
+    on the other) give the results of the same traces run one after the other."""
+    m, om, mesh = tiny
+    o1, d1 = random_interior_rays(50000, 61)
+    o2, d2 = random_interior_rays(60000, 62)
+    tm2 = np.random.default_rng(9).uniform(0.05, 0.5, 60000).astype(np.float32)
+    O1, D1, O2, D2, T2 = _dev(o1), _dev(d1), _dev(o2), _dev(d2), _dev(tm2)
+    ref1 = _host(mesh.trace(O1, D1, want_steps=True))
+    ref2 = _host(mesh.trace(O2, D2, tmax=T2, want_steps=True, sort=2))
+    ws = torch.empty(mesh.workspace_bytes(60000, True, sort=2), dtype=torch.uint8, device="cuda:0")
+    out1 = tetrt.outputs(50000, "cuda:0", want_steps=True)
+    out2 = tetrt.outputs(60000, "cuda:0", want_steps=True)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            mesh.trace_into(out1, O1, D1, stream=s1)
+        with torch.cuda.stream(s2):
+            mesh.trace_into(out2, O2, D2, tmax=T2, sort=2, workspace=ws, stream=s2)
+        torch.cuda.synchronize()
+        got1, got2 = _host(out1), _host(out2)
+        for k in ref1:
+            assert np.array_equal(got1[k], ref1[k], equal_nan=True), k
+        for k in ref2:
+            assert np.array_equal(got2[k], ref2[k], equal_nan=True), k
