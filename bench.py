@@ -79,7 +79,8 @@ def parse():
     ap.add_argument("--sort", type=int, default=0, help="ray binning: 0 auto, 1 off, 2 on")
     ap.add_argument("--sort-chunk", type=int, default=0, help="log2 rays per binning chunk (0 = default)")
     ap.add_argument("--sort-dirq", type=int, default=0, help="direction bins per axis (0 = default)")
-    ap.add_argument("--sort-cells", type=int, default=0, help="log2 origin cells per axis (0 = default)")
+    ap.add_argument("--sort-cells", type=int, default=0,
+                    help="log2 origin cells per axis for binning (0 = by direction only)")
     ap.add_argument("--eye", default="", help="camera position x,y,z (default: the workload's)")
     ap.add_argument("--locate", default="shared", choices=["shared", "per-ray"],
                     help="primary rays: camera located once per pass (shared) or by every ray")

@@ -117,7 +117,8 @@ typedef struct {
                             origin's cell, and traced in that order; the outputs stay at
                             the caller's positions */
     int32_t sort_chunk_log2; /* rays per chunk = 2^this, 10..13 (0 = 12) */
-    int32_t sort_cells_log2; /* origin cells per axis = 2^this, 1..7 (0 = 5) */
+    int32_t sort_cells_log2; /* 0 (default): bins by direction only; 1..7: then by the
+                                origin's cell in a grid of 2^this cells per axis */
     int32_t sort_dirq;   /* direction bins per axis, 1..4 (0 = 4) */
     int32_t xcd_blocks;  /* with xcds > 1: consecutive blocks per die (0 = one contiguous
                             range of the launch per die; > 0 = runs of this many blocks,

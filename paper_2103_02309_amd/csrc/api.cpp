@@ -45,12 +45,12 @@ int sort_config(const tm_mesh_s* m, const tm_trace_opts& o, int64_t n, bool has_
     // automatic: bin batches of secondary-style rays (with tmax) of at least 2^18 rays
     *on = o.sort == 2 || (o.sort == 0 && has_tmax && n >= (int64_t(1) << 18));
     c->chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 12;
-    c->cells_log2 = o.sort_cells_log2 ? o.sort_cells_log2 : 5;
+    c->cells_log2 = o.sort_cells_log2;   // 0: by direction only
     c->dirq = o.sort_dirq ? o.sort_dirq : 4;
-    if (c->chunk_log2 < 10 || c->chunk_log2 > 13 || c->cells_log2 < 1 || c->cells_log2 > 7 ||
+    if (c->chunk_log2 < 10 || c->chunk_log2 > 13 || c->cells_log2 < 0 || c->cells_log2 > 7 ||
         c->dirq < 1 || c->dirq > 4)
         return fail(TM_ERR_ARG, "trace_closest: sort_chunk_log2 must be in [10, 13], sort_cells_log2 "
-                                "in [1, 7] and sort_dirq in [1, 4]");
+                                "in [0, 7] and sort_dirq in [1, 4]");
     const double G = double(int64_t(1) << c->cells_log2);
     for (int a = 0; a < 3; ++a) {
         c->lo[a] = m->lo[a];

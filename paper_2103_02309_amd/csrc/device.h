@@ -63,11 +63,12 @@ struct LaunchCfg {
 hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s);
 
 // Ray binning inside chunks of 2^chunk_log2 consecutive rays: by direction
-// quantised to dirq levels per axis, then by the low bits of the Morton index
-// of the origin's cell in a 2^cells_log2 grid over [lo, lo + G/inv).
+// quantised to dirq levels per axis, then (cells_log2 > 0) by the low bits of
+// the Morton index of the origin's cell in a 2^cells_log2 grid over
+// [lo, lo + G/inv).
 struct SortCfg {
     int32_t chunk_log2;       // 10..13
-    int32_t cells_log2;       // 1..7
+    int32_t cells_log2;       // 0 (direction only) .. 7
     int32_t dirq;             // 1..4
     float lo[3];
     float inv[3];             // cells per unit length, per axis

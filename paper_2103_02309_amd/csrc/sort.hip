@@ -2,8 +2,10 @@
 // usually already coherent in origin (pixel tiles, hit points of neighbouring
 // pixels); what breaks a wavefront's coherence is secondary rays that leave a
 // point in many directions.  So rays are regrouped inside chunks of 2^c
-// consecutive rays: by quantised direction first, then by the low bits of the
-// Morton index of their origin's cell in a grid over the mesh bounds.  Each
+// consecutive rays: by quantised direction, then (optionally) by the low bits
+// of the Morton index of their origin's cell in a grid over the mesh bounds.
+// By default the origin is not used: a chunk of consecutive rays already comes
+// from one small region, and reading the origins would double the bytes read.  Each
 // chunk is counting-sorted by one workgroup in LDS (no global atomics, one pass
 // over the rays), and the walk takes rays through the resulting permutation.
 // The order within a bin is not deterministic; results are per ray and do not
@@ -68,8 +70,11 @@ __device__ void sort_chunk(const SortCfg& c, const float* orig, const float* dir
     __syncthreads();
     for (int r = threadIdx.x; r < cnt; r += 256) {
         const int64_t i = base + r;
-        const uint32_t key = ray_key(c, orig[3 * i], orig[3 * i + 1], orig[3 * i + 2], dir[3 * i],
-                                     dir[3 * i + 1], dir[3 * i + 2]);
+        // with no origin grid (cells_log2 = 0) the origins are not read at all
+        const bool by_origin = c.cells_log2 > 0;
+        const uint32_t key = ray_key(c, by_origin ? orig[3 * i] : 0.0f, by_origin ? orig[3 * i + 1] : 0.0f,
+                                     by_origin ? orig[3 * i + 2] : 0.0f, dir[3 * i], dir[3 * i + 1],
+                                     dir[3 * i + 2]);
         keys[r] = uint16_t(key);
         atomicAdd(&hist[key], 1u);
     }
