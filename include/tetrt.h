@@ -20,7 +20,9 @@
  *     shares the id.  tetmesh_tri_vertices maps an id to its vertices.
  *   - Device pointers are HIP device memory on the current device; host
  *     pointers are ordinary process memory.  The caller owns every buffer it
- *     passes.  No call allocates per ray batch.
+ *     passes.  No call allocates per ray batch.  A call on a mesh, batch or
+ *     server needs the device it was created on to be current (TM_ERR_ARG
+ *     otherwise).
  *   - Work is enqueued on the given HIP stream (NULL = the default stream) and
  *     returns without synchronising.  A handle is read-only after upload, so
  *     traces on different streams may run concurrently.

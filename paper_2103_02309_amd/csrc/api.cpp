@@ -67,6 +67,16 @@ using tetrt::fail;
 using tetrt::hip_fail;
 using tetrt::sort_config;
 
+// Kernels of a mesh run on the device it was uploaded to: that device must be
+// current (its pointers mean nothing on another).
+int check_device(const tm_mesh_s* m, const char* what) {
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != m->device)
+        return fail(TM_ERR_ARG, "%s: mesh on device %d, current device %d", what, m->device, dev);
+    return TM_OK;
+}
+
 void release(tm_mesh_s* m) {
     for (void* p : m->allocations) (void)hipFree(p);
     m->allocations.clear();
@@ -200,6 +210,7 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
                   const tm_trace_opts* opts, void* hip_stream) {
     tetrt::clear_error();
     if (!m) return fail(TM_ERR_ARG, "trace_closest: NULL mesh");
+    if (int rc = check_device(m, "trace_closest")) return rc;
     if (n_rays < 0 || n_rays > int64_t(0x7FFFFFFF))
         return fail(TM_ERR_ARG, "trace_closest: n_rays = %lld out of range [0, 2^31)",
                     (long long)n_rays);
@@ -310,6 +321,7 @@ int tetmesh_bin_rays(tm_mesh m, int64_t n_rays, const float* d_orig, const float
                      const tm_trace_opts* opts, int32_t* d_order, void* hip_stream) {
     tetrt::clear_error();
     if (!m) return fail(TM_ERR_ARG, "tetmesh_bin_rays: NULL mesh");
+    if (int rc = check_device(m, "tetmesh_bin_rays")) return rc;
     if (n_rays < 0 || n_rays > int64_t(0x7FFFFFFF))
         return fail(TM_ERR_ARG, "tetmesh_bin_rays: n_rays = %lld out of range [0, 2^31)", (long long)n_rays);
     if (n_rays == 0) return TM_OK;
@@ -349,6 +361,7 @@ int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_prese
 int tetmesh_locate(tm_mesh m, int64_t n, const float* d_pts, int32_t* d_tet, void* hip_stream) {
     tetrt::clear_error();
     if (!m) return fail(TM_ERR_ARG, "tetmesh_locate: NULL mesh");
+    if (int rc = check_device(m, "tetmesh_locate")) return rc;
     if (n < 0 || n > int64_t(0x7FFFFFFF))
         return fail(TM_ERR_ARG, "tetmesh_locate: n = %lld out of range [0, 2^31)", (long long)n);
     if (n == 0) return TM_OK;
