@@ -141,9 +141,6 @@ __device__ __forceinline__ Rec load_rec(const Mem& M, uint32_t tet) {
     }
 }
 
-// Neighbour field across the face opposite the vertex of rank r (0..3) in a
-// record; `back` is the field of the face the walk entered through and `ra`
-// the rank of the vertex opposite it (used by Tet16 only).
 // Word r (0..3) of four, selected on the bits of r: three selects and no
 // compare chain (which the compiler would turn into a branch).
 __device__ __forceinline__ uint32_t pick4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, int r) {
@@ -169,6 +166,9 @@ __device__ __forceinline__ uint32_t pick4b(uint32_t w0, uint32_t w1, uint32_t w2
     return hi ? b : a;
 }
 
+// Neighbour field across the face opposite the vertex of rank r (0..3) in a
+// record; `back` is the field of the face the walk entered through and `ra`
+// the rank of the vertex opposite it (used by Tet16 only).
 template <int LAYOUT>
 __device__ __forceinline__ uint32_t next_field(const Rec& R, int r, uint32_t back, int ra) {
     if (LAYOUT == kTet16) {
@@ -299,8 +299,10 @@ struct Prec {
 // 1e-16 S (|a|_1 + |b|_1); anything within 1e-14 S (|a|_1 + |b|_1) is a tie.
 constexpr double kTie64 = 1e-14;
 
+// float64 2-D determinant, both products rounded (as det2)
 __device__ __forceinline__ double det2d(double ax, double ay, double bx, double by) {
-    return __dmul_rn(ax, by) - __dmul_rn(ay, bx);
+#pragma clang fp contract(off)
+    return ax * by - ay * bx;
 }
 
 __device__ __forceinline__ void project64(const Frame& f, double pox, double poy, float4 p, double& qx,
