@@ -168,7 +168,7 @@ typedef struct {
  *   opts     host, nullable
  *   out      host; receives the handle (owns all device memory until tetmesh_free)
  * Limits: 1 <= n_tets <= 214,748,364 (134,217,727 with TM_LAYOUT_TET32N: the
- * records and points stay below 4 GiB each), 4 <= n_points <= 268,435,455, fewer
+ * records and points stay below 4 GiB each), 4 <= n_points <= 357,913,941, fewer
  * than 2^31 - 1 constrained triangles.  Inputs are copied; the caller may free them on return.
  * Errors: TM_ERR_ARG, TM_ERR_MESH (with validate = 1: vertex id out of range,
  * repeated vertex, zero volume, neighbour link not mutual, neighbours not

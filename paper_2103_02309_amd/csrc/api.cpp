@@ -128,9 +128,9 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     // is written for
     {
         const int64_t rb = (opts && opts->layout == TM_LAYOUT_TET32N) ? 32 : 20;
-        if (n_tets * rb > int64_t(0xFFFFFFFFLL) || n_points * 16 > int64_t(0xFFFFFFFFLL))
+        if (n_tets * rb > int64_t(0xFFFFFFFFLL) || n_points * 12 > int64_t(0xFFFFFFFFLL))
             return fail(TM_ERR_ARG, "tetmesh_upload: mesh too large (at most %lld tets and %lld points)",
-                        (long long)(0xFFFFFFFFLL / rb), (long long)(0xFFFFFFFFLL / 16));
+                        (long long)(0xFFFFFFFFLL / rb), (long long)(0xFFFFFFFFLL / 12));
     }
     tm_upload_opts o = {TM_LAYOUT_TET20, TM_SFC_HILBERT, 1, 0};
     if (opts) o = *opts;
@@ -168,7 +168,7 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     tetrt::DevMesh& d = m->dev;
     if ((rc = upload_array(m, pm.rec, &d.rec, &hot)) ||
         (!pm.n3.empty() && (rc = upload_array(m, pm.n3, &d.n3, &cold))) ||
-        (rc = upload_array(m, pm.pts4, &d.pts, &hot)) ||
+        (rc = upload_array(m, pm.pts, &d.pts, &hot)) ||
         (rc = upload_array(m, pm.tetv, &d.tetv, &cold)) ||
         (rc = upload_array(m, pm.cfv, &d.cfv, &cold)) ||
         (rc = upload_array(m, pm.cft, &d.cft, &cold)) ||

@@ -15,7 +15,7 @@ struct DevMesh {
                               // [nt*4] Tet16 records (xor field, NX0..NX2) or
                               // [nt*8] Tet32N records (N0..N3, neighbours' xor fields)
     const int32_t* n3;        // [nt]      Tet16 only: N3 of every tet (cold, for starts)
-    const float* pts;         // [np*4]    float4 per point
+    const float* pts;         // [np*3]    x, y, z per point (12 bytes, no padding)
     const int32_t* tetv;      // [nt*4]    ascending vertex ids (int4 per tet)
     const int32_t* cfv;       // [ntri*4]  constrained-face vertices (int4)
     const int32_t* cft;       // [ntri*4]  constrained-face tets and their xor fields (int4)
@@ -129,7 +129,7 @@ struct GenEntry {
     float up[3];
     float light[3];    // shadow: light position
     float ao_tmax;
-    const float* pts;  // mesh points (float4) and constrained-face vertices (int4),
+    const float* pts;  // mesh points (x, y, z) and constrained-face vertices (int4),
     const int32_t* cfv;//   for the normal of the hit triangle
 };
 

@@ -312,12 +312,12 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
     }
 
     // ---- points ----------------------------------------------------------------
-    M.pts4.assign(size_t(4 * np), 0.0f);
+    M.pts.assign(size_t(3 * np), 0.0f);
     for (int64_t i = 0; i < np; ++i) {
         const float* s = P + 3 * (int64_t)p_new2old[i];
-        M.pts4[4 * i] = s[0];
-        M.pts4[4 * i + 1] = s[1];
-        M.pts4[4 * i + 2] = s[2];
+        M.pts[3 * i] = s[0];
+        M.pts[3 * i + 1] = s[1];
+        M.pts[3 * i + 2] = s[2];
     }
 
     // ---- tet records (Tet20, Tet16 or Tet32N) ------------------------------
@@ -427,7 +427,7 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
     for (int64_t tn = 0; tn < nt; ++tn) {
         double c[3] = {0, 0, 0};
         for (int r = 0; r < 4; ++r)
-            for (int a = 0; a < 3; ++a) c[a] += M.pts4[4 * (int64_t)M.tetv[4 * tn + r] + a];
+            for (int a = 0; a < 3; ++a) c[a] += M.pts[3 * (int64_t)M.tetv[4 * tn + r] + a];
         int ci[3];
         double d2 = 0;
         for (int a = 0; a < 3; ++a) {

@@ -16,7 +16,7 @@ constexpr uint32_t kBoundaryField = 0xFFFFFFFFu;
 struct PackedMesh {
     int64_t np = 0, nt = 0, ntri = 0;
     int32_t layout = 0, sfc = 0;
-    std::vector<float> pts4;             // [np*4]   x, y, z, 0 in internal point order
+    std::vector<float> pts;              // [np*3]   x, y, z in internal point order
     std::vector<int32_t> rec;            // Tet20 [nt*5]: xor of the four internal vertex ids, then
                                          //   the neighbour fields N0..N3 by ascending vertex id;
                                          // Tet16 [nt*4]: xor, then NX_j = N_j ^ N_3 for j < 3;

@@ -73,9 +73,12 @@ __device__ void secondary_ray(const GenEntry& g, int64_t i, RayPool p) {
         p.tmax[k] = 1.0f;        // the light is at t = 1
     } else {
         const int4 v = reinterpret_cast<const int4*>(g.cfv)[tri];
-        const float4 A = reinterpret_cast<const float4*>(g.pts)[v.x];
-        const float4 B = reinterpret_cast<const float4*>(g.pts)[v.y];
-        const float4 C = reinterpret_cast<const float4*>(g.pts)[v.z];
+        const float* pa = g.pts + 3 * int64_t(v.x);
+        const float* pb = g.pts + 3 * int64_t(v.y);
+        const float* pc = g.pts + 3 * int64_t(v.z);
+        const float3 A = make_float3(pa[0], pa[1], pa[2]);
+        const float3 B = make_float3(pb[0], pb[1], pb[2]);
+        const float3 C = make_float3(pc[0], pc[1], pc[2]);
         const float e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z;
         const float e2x = C.x - A.x, e2y = C.y - A.y, e2z = C.z - A.z;
         float n[3] = {e1y * e2z - e1z * e2y, e1z * e2x - e1x * e2z, e1x * e2y - e1y * e2x};

@@ -36,7 +36,9 @@
 //          entry vertex's rank xor NX of the exit vertex's rank (NX_3 = 0),
 //          Algorithms 6-7.
 //   With these the point is one 12-byte load after the record, so a step is
-//   two dependent round trips (record, then point).  The next record's load is
+//   two dependent round trips (record, then point).  Points are stored as
+//   12-byte triples, not padded to 16: more of them share a cache line, and
+//   the walk's loads are bound by the L1's line lookups and fills.  The next record's load is
 //   issued inside the step, as soon as the exit face is known.
 //   Tet32N 32 bytes {N0..N3, W0..W3}: the neighbour fields and each
 //          neighbour's xor-sum.  The xor-sum of the tet being entered comes
@@ -106,7 +108,7 @@ template <int LAYOUT>
 __device__ __forceinline__ Mem make_mem(const DevMesh& m) {
     Mem M;
     M.rec = make_rsrc(m.rec, rec_bytes<LAYOUT>(), uint32_t(m.nt));
-    M.pts = make_rsrc(m.pts, 16u, uint32_t(m.np));
+    M.pts = make_rsrc(m.pts, 12u, uint32_t(m.np));
     return M;
 }
 
