@@ -9,7 +9,8 @@ namespace tetrt {
 
 // Plain pointers into device memory owned by a tm_mesh handle; passed to the
 // kernels by value.  Vector-typed arrays are stored as their scalar base type
-// and reinterpreted in the kernels (int4 / float4 / int2, 16- or 8-byte aligned).
+// and reinterpreted in the kernels (int4 / int2, 16- or 8-byte aligned; points
+// are plain x, y, z triples).
 struct DevMesh {
     const int32_t* rec;       // [nt*5] Tet20 records (xor field, N0..N3),
                               // [nt*4] Tet16 records (xor field, NX0..NX2) or
