@@ -250,6 +250,20 @@ def test_layouts_agree(tetrt, tiny_mesh):
             assert np.array_equal(outs[0][k], other[k], equal_nan=True), k
 
 
+@pytest.mark.parametrize("layout,rec_bytes", [("tet20", 20), ("tet16", 16), ("tet32n", 32)])
+def test_hot_bytes_per_layout(tetrt, tiny_mesh, layout, rec_bytes):
+    """The arrays a step reads: one record per tet and one unpadded 12-byte point
+    per vertex."""
+    m = tiny_mesh
+    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=layout)
+    try:
+        info = mesh.info
+        assert info["n_tets"] == m.n_tets and info["n_points"] == m.n_points
+        assert info["hot_bytes"] == rec_bytes * m.n_tets + 12 * m.n_points
+    finally:
+        mesh.free()
+
+
 @pytest.mark.parametrize("kw", [dict(sort=2), dict(sort=2, sort_cells_log2=2, sort_dirq=1),
                                 dict(sort=2, sort_chunk_log2=10, sort_cells_log2=7, sort_dirq=3),
                                 dict(sort=2, sort_chunk_log2=13),
