@@ -950,10 +950,14 @@ k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
         Prec pc{kn.eps, moved[0], moved[1], moved[2], 0};
         pc.allow_degen = attempt == 1;
         pc.degen = degen && attempt == 0;
+        // the pipelined form of walk_ray (next record loaded inside the step)
+        if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
+        Rec R = load_rec<LAYOUT>(M, s.w.next);
         while (!pc.degen && walk_on<TMAX>(s, r.max_steps - steps)) {
-            walk_step<TMAX, LAYOUT, true>(M, s.f, s.g, s.w, pc);
+            walk_step_rec<TMAX, LAYOUT, true, true, true>(M, s.f, s.g, s.w, pc, R, &R);
             ++s.steps;
         }
+        if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
         steps += s.steps;
         n64 += pc.n64;
         if (!pc.degen) break;
