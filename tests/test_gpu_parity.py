@@ -48,7 +48,8 @@ def _ao_from(m, om, o, d, ref, k=8, seed=3, tmax=0.1):
     return ao, ad, atm, ref["tri"][hit][parent].astype(np.int32)
 
 
-KERNELS = [dict(kernel=1), dict(kernel=2), dict(kernel=2, grid_cap=2, refill=8)]
+KERNELS = [dict(kernel=1), dict(kernel=2), dict(kernel=2, grid_cap=2, refill=8),
+           dict(eps=1e-6), dict(eps=1e-4)]   # the last two: the precision variant
 
 
 @pytest.mark.parametrize("kw", KERNELS)
