@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9",
                     help="serve: offered rates as fractions of the measured capacity")
     ap.add_argument("--serve-big", type=int, default=1, help="serve: include the 12.6M-tet mesh")
+    ap.add_argument("--serve-burst", type=int, default=512,
+                    help="serve: requests in the burst that measures capacity")
     ap.add_argument("--batch-meshes", type=int, default=64, help="batch64: number of meshes")
     ap.add_argument("--tile", type=int, default=8, help="pixel tile edge for ray order (1 = row-major)")
     ap.add_argument("--sfc", default="hilbert", choices=["hilbert", "morton", "none"])
@@ -667,8 +669,9 @@ def bench_serve(args, tetrt, dev, log):
 
     srv = tetrt.Server(meshes, max_rays=32 << 20, block=args.block, sort=args.sort)
 
-    # capacity: a burst of requests, drained
-    burst = [request() for _ in range(64)]
+    # capacity: a burst of requests, drained (long enough that its mix of sizes
+    # is close to the stream's)
+    burst = [request() for _ in range(args.serve_burst)]
     for _ in range(2):
         for k, r in enumerate(burst):
             srv.submit(view(bufs[k % n_buf], r["width"] * r["height"]), **r)
