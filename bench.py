@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--serve-big", type=int, default=1, help="serve: include the 12.6M-tet mesh")
     ap.add_argument("--serve-burst", type=int, default=512,
                     help="serve: requests in the burst that measures capacity")
+    ap.add_argument("--serve-ring", type=int, default=0,
+                    help="serve: launches in flight (0 = the library's default, 1)")
     ap.add_argument("--batch-meshes", type=int, default=64, help="batch64: number of meshes")
     ap.add_argument("--tile", type=int, default=8, help="pixel tile edge for ray order (1 = row-major)")
     ap.add_argument("--sfc", default="hilbert", choices=["hilbert", "morton", "none"])
@@ -667,7 +669,7 @@ def bench_serve(args, tetrt, dev, log):
     def view(b, n):
         return {"tri": b["tri"][:n], "t": b["t"][:n], "bary": b["bary"][:n]}
 
-    srv = tetrt.Server(meshes, max_rays=32 << 20, block=args.block, sort=args.sort)
+    srv = tetrt.Server(meshes, max_rays=32 << 20, block=args.block, sort=args.sort, ring=args.serve_ring)
 
     # capacity: a burst of requests, drained (long enough that its mix of sizes
     # is close to the stream's)
@@ -738,7 +740,8 @@ def bench_serve(args, tetrt, dev, log):
         "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "16 meshes (%d tets), Poisson requests: interior camera, "
                                "64^2..1024^2, primary/shadow/AO 50/25/25%%" % tets,
-                   "layout": args.layout, "seconds_per_load": args.serve_seconds},
+                   "layout": args.layout, "seconds_per_load": args.serve_seconds,
+                   "capacity_burst": args.serve_burst, "ring": args.serve_ring or 1},
         "capacity": {"requests_s": round(cap_rps, 1), "mrays_s": round(burst_rays / burst_s / 1e6, 2)},
         "loads": loads,
     }

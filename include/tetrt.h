@@ -376,7 +376,7 @@ typedef struct {
     int64_t max_rays;     /* ray pool slots (one per pixel of every admitted request),
                              1 <= max_rays <= 2^31 - 1; 48 bytes of device memory each */
     int32_t max_requests; /* admitted requests at once, 1..65536 (0 = 4096) */
-    int32_t ring;         /* launches in flight, 1..8 (0 = 3) */
+    int32_t ring;         /* launches in flight, 1..8 (0 = 1) */
     int32_t block;        /* as tm_trace_opts */
     int32_t sort;
     int32_t max_steps;

@@ -326,7 +326,9 @@ int tm_server_create(const tm_mesh* meshes, int32_t n_meshes, const tm_server_op
         return fail(TM_ERR_ARG, "tm_server_create: max_rays = %lld out of range [1, 2^31)",
                     (long long)o.max_rays);
     if (o.max_requests == 0) o.max_requests = 4096;
-    if (o.ring == 0) o.ring = 3;
+    // one launch in flight: each step then carries every request that arrived
+    // during the previous launch (lowest latency measured at up to 75% load)
+    if (o.ring == 0) o.ring = 1;
     if (o.max_requests < 1 || o.max_requests > 65536)
         return fail(TM_ERR_ARG, "tm_server_create: max_requests out of range [1, 65536]");
     if (o.ring < 1 || o.ring > 8) return fail(TM_ERR_ARG, "tm_server_create: ring out of range [1, 8]");
