@@ -97,6 +97,12 @@ def test_primary_sampled_vs_oracle(paper):
     same = sub["tri"] == ref["tri"]
     assert np.array_equal(sub["hit_tets"][same & (ref["tri"] >= 0)], ref["tets"][same & (ref["tri"] >= 0)])
     assert (sub["steps"] == ref["steps"]).mean() > 0.99
+    # the precision variant on the same rays meets the same bar
+    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), block=256, eps=1e-6)
+    torch.cuda.synchronize()
+    sub = {k: v.cpu().numpy()[idx] for k, v in res.items()}
+    rep = compare(m.points, om.tri_verts, o[idx], d[idx], ref, sub)
+    assert rep["ok"], ("eps 1e-6", rep)
 
 
 def test_ao_sampled_vs_oracle(paper):
@@ -126,6 +132,13 @@ def test_ao_sampled_vs_oracle(paper):
     torch.cuda.synchronize()
     for k, v in res.items():
         assert np.array_equal(v.cpu().numpy(), g[k], equal_nan=True), k
+    # the precision variant on the same rays meets the same bar
+    res = mesh.trace(torch.from_numpy(ao).cuda(), torch.from_numpy(ad).cuda(),
+                     tmax=torch.from_numpy(atm).cuda(), start_face=torch.from_numpy(sf).cuda(), sort=2,
+                     eps=1e-6)
+    torch.cuda.synchronize()
+    rep = compare(m.points, om.tri_verts, ao, ad, ref, {k: v.cpu().numpy() for k, v in res.items()}, tmax=atm)
+    assert rep["ok"], ("eps 1e-6", rep)
 
 
 def test_ao_from_device_hits_properties(paper):
