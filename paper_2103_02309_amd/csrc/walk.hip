@@ -882,9 +882,9 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
 // One lane per ray: set-up, walk, result.
 // 8 waves per SIMD (at most 64 VGPRs): the walk is latency-bound, so occupancy
 // is what hides the memory round trips.  The precision variant carries float64
-// code; it runs 6 waves (without tmax) or 4 (with), the most at which its step
-// loop keeps every value in registers: the spilled values are those of the
-// rare float64 paths and of set-up.
+// code; it runs 7 waves (without tmax) or 4 (with): at these register budgets
+// its step loop keeps every value in registers, and the spilled values are
+// those of the rare float64 paths and of set-up.
 // The dispatcher deals blocks to the XCDs round-robin (block b runs on XCD
 // b mod X), and each XCD has an L2 of its own.  Renumbering blocks so that
 // consecutive ones share an XCD keeps neighbouring rays -- which visit the same
@@ -909,7 +909,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t 
 }
 
 template <bool TMAX, int LAYOUT, bool PREC, bool STEPS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? (TMAX ? 4 : 6) : 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? (TMAX ? 4 : 7) : 8)))
 k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds, kn.xcd_blocks)) * blockDim.x + threadIdx.x;
     if (j >= r.n) return;
