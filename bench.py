@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--tile", type=int, default=8, help="pixel tile edge for ray order (1 = row-major)")
     ap.add_argument("--sfc", default="hilbert", choices=["hilbert", "morton", "none"])
     ap.add_argument("--layout", default="tet16", choices=["tet20", "tet16", "tet32n"])
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=0, help="threads per block (0 = the library's choice)")
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 one lane per ray, 2 persistent")
     ap.add_argument("--refill", type=int, default=0, help="persistent refill threshold (0 = default)")
     ap.add_argument("--ao", type=int, default=8, help="AO rays per primary hit")
@@ -287,7 +287,8 @@ def main():
             "tets": m.n_tets, "points": m.n_points, "triangles": info["n_tris"],
             "primary_rays": n_p, "ao_rays": n_a, "ray_order": "8x8 tiles" if args.tile == 8 else
             ("row-major" if args.tile <= 1 else "%dx%d tiles" % (args.tile, args.tile)),
-            "layout": args.layout, "sfc": args.sfc, "block": args.block,
+            "layout": args.layout, "sfc": args.sfc,
+            "block": args.block or "auto (128 primary, 256 binned AO)",
             "kernel": {0: "auto", 1: "one lane per ray", 2: "persistent lanes"}[args.kernel],
             "ray_binning": {0: "auto (AO rays)", 1: "off", 2: "on"}[args.sort], "eye": list(eye),
             "precision_eps": args.eps,
@@ -373,7 +374,7 @@ def measured_counters(args):
     None for each when the summary was taken on other kernel sources or another
     setup."""
     keys = ("traffic_bytes_per_launch", "l1_accesses_per_launch", "l2_requests_per_launch", "l2_hit_rate")
-    if (args.layout != "tet16" or args.sfc != "hilbert" or args.sort != 0 or args.block != 256 or args.eps > 0
+    if (args.layout != "tet16" or args.sfc != "hilbert" or args.sort != 0 or args.block not in (0, 256) or args.eps > 0
             or args.kernel not in (0, 1)):
         return (None,) * len(keys)
     vals = summary_values(TRAFFIC_SUMMARY, keys + ("kernel_source_sha256",))

@@ -100,7 +100,8 @@ typedef struct {
 /* Options for trace_closest; pass NULL for the defaults (all fields 0). */
 typedef struct {
     int32_t max_steps;   /* walk step cap per ray (tets entered); 0 = 65536 */
-    int32_t block;       /* threads per block: 64, 128 or 256 (0 = 256) */
+    int32_t block;       /* threads per block: 64, 128 or 256 (0 = automatic: 256 when the
+                            rays are binned or in a caller's order, else 128) */
     int32_t kernel;      /* 0 = automatic, 1 = one lane per ray, 2 = persistent lanes that
                             take further rays as theirs finish */
     int32_t refill;      /* persistent lanes: finished lanes per wavefront that trigger a

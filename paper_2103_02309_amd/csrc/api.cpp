@@ -259,7 +259,11 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
     r.n = n_rays;
     r.max_steps = o.max_steps > 0 ? o.max_steps : 65536;
     tetrt::LaunchCfg c;
-    c.block = o.block ? o.block : 256;
+    // automatic: 256-thread blocks for binned (or caller-ordered) rays, 128 for
+    // the rest, whose walks differ more in length from lane to lane; smaller
+    // blocks retire sooner and even out the XCDs' loads (camera rays: 0.834 vs
+    // 0.853 ms; binned AO rays: 1.396 vs 1.340 ms)
+    c.block = o.block ? o.block : ((binned || o.order) ? 256 : 128);
     c.cus = m->cus;
     c.waves_per_simd = 8;
     c.refill = o.refill ? o.refill : 16;
