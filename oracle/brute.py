@@ -52,7 +52,7 @@ def brute_closest_hit(points, tri_verts, orig, dirs, tmax=None, exclude=None,
             qvec = np.cross(sv, e1[None])
             v = np.einsum("nfk,nfk->nf", np.broadcast_to(d, qvec.shape), qvec) * inv
             t = np.einsum("nfk,fk->nf", qvec, e2) * inv
-        ok = (det != 0.0) & (u >= 0.0) & (v >= 0.0) & (u + v <= 1.0) & (t > 0.0)
+            ok = (det != 0.0) & (u >= 0.0) & (v >= 0.0) & (u + v <= 1.0) & (t > 0.0)
         ok &= t <= tm_all[s:s + step, None]
         ok &= fid[None, :] != ex_all[s:s + step, None]
         tt = np.where(ok, t, np.inf)

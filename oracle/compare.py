@@ -2,11 +2,16 @@
 
 Acceptance, per ray set:
   * identical triangle id (or the same miss/abort code) for >= 99.99% of rays;
-  * every other ray is explained: its hit point (the oracle's, or the point
-    where the ray meets the other side's triangle) lies within ``edge_tol``
-    (relative to the scene extent) of an edge or vertex of the oracle's or the
-    compared triangle -- several ids are then correct -- or, for a hit/miss
-    disagreement, the hit's t is within ``tmax_rtol`` of tmax;
+  * every other ray is explained, by one of:
+      - the oracle hit triangle R, and its FP64 hit point lies within ``edge_tol``
+        (relative to the scene extent) of an edge or vertex of R or of the
+        compared triangle G; G, if any, is not nearer along the ray than R (to
+        ``t_rtol``) -- the ray meets an edge where several ids are correct, or
+        grazes R's edge and goes on to G;
+      - G is nearer than R (or the oracle misses), and the point where the ray
+        meets G's plane lies within ``edge_tol`` of an edge or vertex of G -- the
+        ray grazes G's edge, which the oracle passed;
+      - a hit/miss disagreement whose hit has t within ``tmax_rtol`` of tmax;
   * matched hits: |dt| / t <= ``t_rtol`` and |d bary| <= ``bary_tol``;
   * no step-cap (-2) or invalid (-3) code on rays the oracle traces normally.
 """
@@ -100,23 +105,46 @@ def compare(points, tri_verts, orig, dirs, ref, got, tmax=None, extent=1.0, edge
         r_hit, g_hit = rt[mism] >= 0, gt[mism] >= 0
         ref_h = mo + np.asarray(ref["t"])[mism][:, None] * md
         near = np.zeros(mism.size, dtype=bool)
+        rtv = np.asarray(ref["t"], np.float64)[mism]
+        gtv = np.asarray(got["t"], np.float64)[mism]
+        with np.errstate(invalid="ignore"):
+            # the compared hit is nearer along the ray than the oracle's (or the oracle misses)
+            g_nearer = g_hit & (~r_hit | (gtv < rtv * (1.0 - t_rtol)))
         if r_hit.any():
-            idx = np.nonzero(r_hit)[0]
-            near[idx] |= _edge_distance(P, tri_verts, rt[mism][idx], ref_h[idx]) <= tol
-        if g_hit.any():
-            idx = np.nonzero(g_hit)[0]
-            # the ray's point on the other triangle's plane, and on the oracle's
+            # the oracle's FP64 hit point on an edge of its own triangle or of G
+            idx = np.nonzero(r_hit & ~g_nearer)[0]
+            if idx.size:
+                e = _edge_distance(P, tri_verts, rt[mism][idx], ref_h[idx]) <= tol
+                gi = g_hit[idx]
+                if gi.any():
+                    both = idx[gi]
+                    e[gi] |= _edge_distance(P, tri_verts, gt[mism][both], ref_h[both]) <= tol
+                near[idx] = e
+        if g_nearer.any():
+            # the ray grazes an edge of G, which the oracle passed
+            idx = np.nonzero(g_nearer)[0]
             gh = _plane_point(P, tri_verts, gt[mism][idx], mo[idx], md[idx])
-            near[idx] |= _edge_distance(P, tri_verts, gt[mism][idx], gh) <= tol
-            both = idx[r_hit[idx]]
-            if both.size:
-                near[both] |= _edge_distance(P, tri_verts, gt[mism][both], ref_h[both]) <= tol
+            near[idx] = _edge_distance(P, tri_verts, gt[mism][idx], gh) <= tol
+        if g_hit.any():
+            # whatever the case, G itself lies on the ray (its line passes within tol of
+            # G's closed triangle) at the reported t
+            idx = np.nonzero(g_hit)[0]
+            gap = ray_triangle_gap(P, tri_verts, gt[mism][idx], mo[idx], md[idx])
+            tv = np.asarray(tri_verts)[gt[mism][idx]]
+            A, B, Cc = P[tv[:, 0]], P[tv[:, 1]], P[tv[:, 2]]
+            nrm = np.cross(B - A, Cc - A)
+            with np.errstate(invalid="ignore", divide="ignore"):
+                tpl = np.einsum("ij,ij->i", nrm, A - mo[idx]) / np.einsum("ij,ij->i", nrm, md[idx])
+                on_ray = (gap <= tol) & (np.abs(gtv[idx] - tpl) <= t_rtol * np.abs(tpl) + tol)
+            near[idx] &= on_ray
         # hit/miss at tmax
         tm_m = tm[mism]
         with np.errstate(invalid="ignore"):
-            rtm = r_hit & ~g_hit & (np.abs(np.asarray(ref["t"])[mism] - tm_m) <= tmax_rtol * tm_m)
-            gtv = np.asarray(got["t"], dtype=np.float64)[mism]
-            gtm = g_hit & ~r_hit & (np.abs(gtv - tm_m) <= tmax_rtol * tm_m)
+            fin = np.isfinite(tm_m)
+            rtm = r_hit & ~g_hit & fin & (np.abs(rtv - tm_m) <= tmax_rtol * tm_m)
+            gtm = g_hit & ~r_hit & fin & (np.abs(gtv - tm_m) <= tmax_rtol * tm_m)
+            # a reported hit never lies beyond tmax
+            near &= ~(g_hit & (gtv > tm_m * (1.0 + tmax_rtol)))
         explained = (near | rtm | gtm) & ~bad_code[mism]
     rep["mismatches"] = int(mism.size)
     rep["unexplained"] = mism[~explained].tolist()[:50]

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import kuhn_mesh, pinhole_rays, random_interior_rays, ao_rays, tri_geometry
+from synth import kuhn_mesh, pinhole_rays, random_interior_rays, ao_rays, tri_geometry, precision_rays
 from synth.kuhn import random_spheres
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -107,21 +107,45 @@ def _read_golden(name):
     return rows
 
 
-def test_golden_cube_box():
+def _golden_box(split):
+    """The closed Kuhn box of the golden files: every cube boundary face is scene
+    geometry; with ``split`` also the interior face (0,4,7) between t0 and t1."""
     m = kuhn_mesh(1, jitter=0.0)
-    cf = (m.nbrs < 0).astype(np.uint8)          # every boundary face is scene geometry
-    om = oracle.OracleMesh(m.points, m.tets, m.nbrs, cf)
-    assert om.ntri == 12
-    rows = _read_golden("kuhn_cube_box.txt")
+    assert m.tets[0].tolist() == [0, 4, 6, 7] and m.tets[1].tolist() == [0, 4, 7, 5]
+    cf = (m.nbrs < 0).astype(np.uint8)
+    if split:
+        j0 = int(np.nonzero(m.tets[0] == 6)[0][0])     # t0's face opposite vertex 6
+        j1 = int(np.nonzero(m.tets[1] == 5)[0][0])     # t1's face opposite vertex 5
+        assert m.nbrs[0, j0] == 1 and m.nbrs[1, j1] == 0
+        cf[0, j0] = cf[1, j1] = 1
+    return m, oracle.OracleMesh(m.points, m.tets, m.nbrs, cf)
+
+
+@pytest.mark.parametrize("name,split,ntri", [("kuhn_cube_box.txt", False, 12),
+                                             ("kuhn_cube_split.txt", True, 13)])
+@pytest.mark.parametrize("max_steps", [0, 1])
+def test_golden_cube_box(name, split, ntri, max_steps):
+    """Hand-derived hits, step counts, start tets and front/back tets.  With a cap
+    of one step, the rays whose walk takes two steps are answered by the oracle's
+    fallback (the closest hit by its definition, steps = -1) and must give the
+    same triangle, t, weights and tets."""
+    m, om = _golden_box(split)
+    assert om.ntri == ntri
+    rows = _read_golden(name)
     inp = np.array([r[0] for r in rows])
     exp = np.array([r[1] for r in rows])
-    r = om.trace(inp[:, 0:3], inp[:, 3:6], inp[:, 6])
+    r = om.trace(inp[:, 0:3], inp[:, 3:6], inp[:, 6], max_steps=max_steps)
     assert r["tri"].tolist() == exp[:, 0].astype(int).tolist()
     hit = exp[:, 0] >= 0
     assert np.allclose(r["t"][hit], exp[hit, 1], rtol=1e-14, atol=0)
     assert np.allclose(r["bary"][hit], exp[hit, 2:4], atol=1e-14)
-    assert r["steps"].tolist() == exp[:, 4].astype(int).tolist()
+    steps = exp[:, 4].astype(int)
+    if max_steps:
+        assert (steps > max_steps).any()
+        steps = np.where(steps > max_steps, -1, steps)
+    assert r["steps"].tolist() == steps.tolist()
     assert r["start"].tolist() == exp[:, 5].astype(int).tolist()
+    assert r["tets"].tolist() == exp[:, 6:8].astype(int).tolist()
 
 
 # ---- against brute force ---------------------------------------------------------
@@ -182,6 +206,107 @@ def test_secondary_rays_vs_brute(tiny_mesh, tiny_oracle):
     sf = r["tri"][hit][parent]
     _check_vs_brute(tiny_oracle, tiny_mesh.points, ao, ad, atm, start_face=sf, t_rtol=1e-9,
                     bary_tol=1e-8)
+
+
+def _check_hit_tets(om, points, dirs, r):
+    """Front/back tets of every hit: the two tets of the hit face, the front one
+    on the side the ray comes from (its fourth vertex lies against the direction)."""
+    hit = np.nonzero(r["tri"] >= 0)[0]
+    P = np.asarray(points, np.float64)
+    tv = om.tri_verts[r["tri"][hit]]
+    A = P[tv[:, 0]]
+    nf = np.cross(P[tv[:, 1]] - A, P[tv[:, 2]] - A)
+    nd = np.einsum("ij,ij->i", nf, np.asarray(dirs, np.float64)[hit])
+    pair = om.tri_tets[r["tri"][hit]]
+    front, back = r["tets"][hit, 0], r["tets"][hit, 1]
+    assert np.all(np.sort(np.stack([front, back], 1), 1) == np.sort(pair, 1))
+    off = np.array([[v for v in om.tets[t] if v not in f][0] for t, f in zip(front, tv)])
+    side = np.einsum("ij,ij->i", nf, P[off] - A)
+    assert np.all(side * nd < 0)
+
+
+def _fallback_vs_brute(om, points, o, d, tmax=None, start_face=None):
+    """Rays traced with a cap of one step: every ray whose walk needs more takes the
+    oracle's fallback.  Against brute force: the same id (both take the lowest id
+    among hits within 1e-12 of the nearest), t to 1e-12 relative, weights to 1e-10."""
+    r = om.trace(o, d, tmax, start_face=start_face, max_steps=1)
+    fb = r["steps"] == -1
+    assert fb.mean() > 0.5
+    bt, btt, bb = oracle.brute_closest_hit(points, om.tri_verts, o, d, tmax, exclude=start_face)
+    assert np.array_equal(r["tri"][fb], bt[fb])
+    h = fb & (bt >= 0)
+    assert h.sum() > 100
+    assert np.all(np.abs(r["t"][h] - btt[h]) <= 1e-12 * np.abs(btt[h]))
+    assert np.all(np.abs(r["bary"][h] - bb[h]) <= 1e-10)
+    _check_hit_tets(om, points, d, r)
+    return r
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_fallback_vs_brute_degenerate_rays(tiny_mesh, tiny_oracle, kind):
+    """Rays aimed through mesh vertices (kind 1) and along tet edges (kind 2): many
+    hit where several triangles meet, so the tie rule decides the id."""
+    m = tiny_mesh
+    o, d, k = precision_rays(m.points, m.tets, m.cflag, n=20000, seed=4)
+    s = k == kind
+    r = _fallback_vs_brute(tiny_oracle, m.points, o[s], d[s])
+    # the fallback agrees with the walk wherever the walk finishes normally
+    w = tiny_oracle.trace(o[s], d[s])
+    ok = w["steps"] >= 0
+    same = ok & (w["tri"] == r["tri"])
+    assert same.sum() > 0.95 * ok.sum()
+    assert np.array_equal(w["tets"][same], r["tets"][same])
+
+
+def test_fallback_vs_brute_secondary(tiny_mesh, tiny_oracle):
+    """Secondary rays leaving hit faces, half of them into the sphere (every one of
+    those hits its far side): the fallback must exclude the start face."""
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 16, 16, 60.0)
+    r0 = tiny_oracle.trace(o, d)
+    hit = r0["tri"] >= 0
+    hp = o[hit].astype(np.float64) + r0["t"][hit, None] * d[hit].astype(np.float64)
+    nrm, _ = tri_geometry(tiny_mesh.points, tiny_oracle.tri_verts[r0["tri"][hit]])
+    inward = np.where((np.arange(hit.sum()) % 2 == 0)[:, None], -d[hit], d[hit])
+    ao, ad, atm, parent = ao_rays(hp, nrm, inward, k=8, seed=3, tmax=np.inf)
+    sf = r0["tri"][hit][parent]
+    r = _fallback_vs_brute(tiny_oracle, tiny_mesh.points, ao, ad, atm, start_face=sf)
+    w = tiny_oracle.trace(ao, ad, atm, start_face=sf)
+    assert np.array_equal(w["tri"], r["tri"])
+    h = w["tri"] >= 0
+    assert np.array_equal(w["tets"][h], r["tets"][h])
+
+
+def test_fallback_ties_go_to_lowest_id():
+    """Jitter-free grid, rays along +z whose x - y is a multiple of the cell size:
+    each meets the surface exactly on the diagonal edge that two triangles of one
+    cell face share (coordinates dyadic, so both triangles contain the point
+    exactly).  The closest hit is then tied; the definition gives it the lower id."""
+    m = kuhn_mesh(16, jitter=0.0)
+    om = oracle.OracleMesh.from_kuhn(m)
+    rng = np.random.default_rng(12)
+    k = 2000
+    a = np.round(rng.uniform(0.2, 0.8, k) * 2 ** 20) / 2 ** 20
+    c = rng.integers(-3, 4, k) / 16.0
+    o = np.stack([a, a - c, np.full(k, 0.03125)], 1).astype(np.float32)
+    d = np.tile(np.array([[0, 0, 1]], np.float32), (k, 1))
+    r = om.trace(o, d, max_steps=1)
+    assert np.all(r["steps"] == -1)
+    bt, btt, _ = oracle.brute_closest_hit(m.points, om.tri_verts, o, d)
+    assert np.array_equal(r["tri"], bt)
+    # the tie is real: with the reported triangle excluded, another is hit at the same t
+    hit = np.nonzero(bt >= 0)[0][:300]
+    t2, tt2, _ = oracle.brute_closest_hit(m.points, om.tri_verts, o[hit], d[hit], exclude=bt[hit])
+    tied = (t2 >= 0) & (np.abs(tt2 - btt[hit]) <= 1e-12)
+    assert tied.sum() > 100
+    assert np.all(t2[tied] > bt[hit][tied])
+
+
+def test_walk_hit_tets(tiny_mesh, tiny_oracle):
+    """The walk's own front/back tets on the camera rays and random rays."""
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 32, 32, 60.0)
+    _check_hit_tets(tiny_oracle, tiny_mesh.points, d, tiny_oracle.trace(o, d))
+    o, d = random_interior_rays(2000, 17)
+    _check_hit_tets(tiny_oracle, tiny_mesh.points, d, tiny_oracle.trace(o, d))
 
 
 # ---- closed forms on jitter-free grids ------------------------------------------

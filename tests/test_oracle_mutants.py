@@ -29,6 +29,14 @@ MUTANTS = {
                   "m->face_tri[4 * (int64_t)nb + mirror] = id + 1 < (int32_t)nflag ? id + 1 : id;"),
     # the start-face branch must put the face in counter-clockwise order (in the
     # located branch the outward-ordered exit face already is, so no mutant there)
+    # the fallback that answers rays whose walk reaches the step cap (closest hit by
+    # its definition) and the front/back tets of a hit
+    "fallback_tie_to_latest": ("if (t < bt - 1e-12 || (fabs(t - bt) <= 1e-12 && f < best)) {",
+                               "if (t < bt + 1e-12) {"),
+    "fallback_keeps_start_face": ("if (f == exclude) continue;", ""),
+    "fallback_hit_behind_origin": ("!(t > 0.0) || t > tm", "!(t > -1e-3) || t > tm"),
+    "fallback_front_back_swapped": ("tets2[0] = ta_ahead ? tb : ta;", "tets2[0] = ta_ahead ? ta : tb;"),
+    "walk_front_back_swapped": ("tets2[0] = cur; tets2[1] = nxt;", "tets2[0] = nxt; tets2[1] = cur;"),
     "ccw_not_enforced": ("            if (o2 < 0.0) {\n                int32_t ti = a[1]; a[1] = a[2]; a[2] = ti;\n                double t0 = q[1][0], t1 = q[1][1];\n                q[1][0] = q[2][0]; q[1][1] = q[2][1]; q[2][0] = t0; q[2][1] = t1;\n            }\n            nxt = start;",
                          "            nxt = start;"),
 }
