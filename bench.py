@@ -484,6 +484,45 @@ def bench_precision(args, tetrt, dev, log):
           flush=True)
 
 
+_PROBE_MODES = {"random": 0, "8_lanes": 1, "one_line": 2}
+_probe = None
+
+
+def probe_lib():
+    """The benchmark's L1 calibration kernel, libtetrt_probe.so (a library of its
+    own, not part of the traversal library), built if absent."""
+    global _probe
+    if _probe is None:
+        import ctypes as C
+        from paper_2103_02309_amd.build import PROBE_LIB, build_probe
+        if not os.path.exists(PROBE_LIB):
+            build_probe(force=True)
+        L = C.CDLL(PROBE_LIB)
+        vp, i32 = C.c_void_p, C.c_int32
+        L.tetrt_probe_l1.argtypes = [vp, C.c_uint64, i32, C.c_uint32, C.c_uint32, i32, i32, vp, vp]
+        L.tetrt_probe_l1.restype = i32
+        L.tetrt_probe_last_error.argtypes = []
+        L.tetrt_probe_last_error.restype = C.c_char_p
+        _probe = L
+    return _probe
+
+
+def probe_l1(buf, mode, unit_bytes, units, blocks, iters, out, stream=None):
+    """Enqueue the L1 calibration kernel (buf: device bytes, out: a device tensor of
+    blocks * 256 * 16 bytes) on stream (default: torch's current one); the caller
+    times it."""
+    import torch
+    if not buf.is_cuda or not out.is_cuda or out.numel() * out.element_size() < blocks * 256 * 16:
+        raise ValueError("probe_l1: device buffers, out of at least blocks * 4096 bytes")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    L = probe_lib()
+    rc = L.tetrt_probe_l1(buf.data_ptr(), buf.numel() * buf.element_size(), _PROBE_MODES[mode],
+                          int(unit_bytes), int(units), int(blocks), int(iters), out.data_ptr(),
+                          st.cuda_stream)
+    if rc != 0:
+        raise RuntimeError("tetrt_probe_l1 %d: %s" % (rc, L.tetrt_probe_last_error().decode()))
+
+
 def bench_l1probe(args, tetrt, dev, log):
     """The L1's line-lookup rate for wave loads of 16 bytes per lane, by address
     spread: random 128-byte lines (each lane its own line) in L1-resident,
@@ -509,7 +548,7 @@ def bench_l1probe(args, tetrt, dev, log):
         ms = []
         for rep in range(args.warmup + args.steps):
             a.record(st)
-            tetrt.tetrt_probe_l1(buf, mode, ub, units, blocks, iters, out, st)
+            probe_l1(buf, mode, ub, units, blocks, iters, out, st)
             b.record(st)
             b.synchronize()
             if rep >= args.warmup:

@@ -465,28 +465,6 @@ const char* tm_last_error(void);
  * curve", AIP Conf. Proc. 707, 2004). */
 int tetrt_sfc_keys(int32_t curve, int32_t bits, int64_t n, const uint32_t* xyz, uint64_t* out);
 
-/* ---- calibration ----------------------------------------------------------
- * tetrt_probe_l1 -- a measurement kernel, not part of the traversal: it
- * gives the rate at which a CU's vector L1 serves wave loads whose 64 lanes
- * each read 16 bytes (the access shape of a walk step's record and point
- * reads), so that the benchmark can state the walk's cache-line access rate
- * against it.  Every lane of `blocks` 256-thread blocks issues `iters`
- * independent 16-byte loads from d_buf (device, buf_bytes bytes, read only)
- * at the start of unit u of `units` units of `unit_bytes` bytes:
- *   TM_PROBE_RANDOM   u pseudo-random per lane (a wave touches up to 64 units);
- *   TM_PROBE_8_LANES  eight consecutive lanes per unit (8 units per wave load);
- *   TM_PROBE_ONE_LINE one unit per wave load.
- * d_out: device, blocks * 256 * 16 bytes, receives per-lane sums (so the loads
- * stay).  Enqueued on hip_stream (NULL = default); the caller times it.
- * TM_ERR_ARG: unknown mode, unit_bytes not a multiple of 16, units not a power
- * of two, units * unit_bytes > buf_bytes, blocks or iters outside [1, 2^20],
- * NULL buffers. */
-#define TM_PROBE_RANDOM 0
-#define TM_PROBE_8_LANES 1
-#define TM_PROBE_ONE_LINE 2
-int tetrt_probe_l1(const void* d_buf, uint64_t buf_bytes, int32_t mode, uint32_t unit_bytes,
-                   uint32_t units, int32_t blocks, int32_t iters, void* d_out, void* hip_stream);
-
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ PyTorch supplies device memory and the current stream.
 """
 from .binding import (TetRTError, Mesh, upload, tetmesh_upload, trace_closest, tetmesh_locate,
                       tetmesh_tri_vertices, tetmesh_info, tetmesh_free, tm_last_error,
-                      tetrt_sfc_keys, tetrt_probe_l1, tetmesh_trace_workspace, tetmesh_bin_rays, library_path, RAY_MISS, RAY_STEP_CAP, RAY_INVALID,
+                      tetrt_sfc_keys, tetmesh_trace_workspace, tetmesh_bin_rays, library_path, RAY_MISS, RAY_STEP_CAP, RAY_INVALID,
                       Batch, outputs, tm_batch_create, tm_batch_set, tm_batch_launch,
                       tm_batch_graph_launch, tm_batch_tune, tm_batch_free, Server,
                       tm_server_create, tm_server_submit, tm_server_step, tm_server_poll,
@@ -17,7 +17,7 @@ from .binding import (TetRTError, Mesh, upload, tetmesh_upload, trace_closest, t
 
 __all__ = ["TetRTError", "Mesh", "upload", "tetmesh_upload", "trace_closest", "tetmesh_locate",
            "tetmesh_tri_vertices", "tetmesh_info", "tetmesh_free", "tm_last_error",
-           "tetrt_sfc_keys", "tetrt_probe_l1", "tetmesh_trace_workspace", "tetmesh_bin_rays", "library_path", "RAY_MISS", "RAY_STEP_CAP", "RAY_INVALID",
+           "tetrt_sfc_keys", "tetmesh_trace_workspace", "tetmesh_bin_rays", "library_path", "RAY_MISS", "RAY_STEP_CAP", "RAY_INVALID",
            "Batch", "outputs", "tm_batch_create", "tm_batch_set", "tm_batch_launch",
            "tm_batch_graph_launch", "tm_batch_tune", "tm_batch_free", "Server",
            "tm_server_create", "tm_server_submit", "tm_server_step", "tm_server_poll",

@@ -132,8 +132,6 @@ def _load():
     L.tetmesh_free.argtypes = [vp]
     L.tetrt_sfc_keys.restype = C.c_int
     L.tetrt_sfc_keys.argtypes = [i32, i32, i64, vp, vp]
-    L.tetrt_probe_l1.argtypes = [vp, C.c_uint64, i32, C.c_uint32, C.c_uint32, i32, i32, vp, vp]
-    L.tetrt_probe_l1.restype = i32
     L.tm_batch_create.restype = C.c_int
     L.tm_batch_create.argtypes = [i32, i64, C.POINTER(vp)]
     L.tm_batch_set.restype = C.c_int
@@ -290,19 +288,6 @@ def tetrt_sfc_keys(xyz, bits=21, curve="hilbert"):
     _check(_load().tetrt_sfc_keys(_SFC[curve], int(bits), xyz.shape[0], xyz.ctypes.data,
                                   out.ctypes.data))
     return out
-
-
-_PROBE = {"random": 0, "8_lanes": 1, "one_line": 2}
-
-
-def tetrt_probe_l1(buf, mode, unit_bytes, units, blocks, iters, out, stream=None):
-    """Enqueue the L1 calibration kernel (``buf``: device bytes, ``out``: device
-    tensor of ``blocks * 256 * 16`` bytes); the caller times it."""
-    if not buf.is_cuda or not out.is_cuda or out.numel() * out.element_size() < blocks * 256 * 16:
-        raise ValueError("tetrt_probe_l1: device buffers, out of at least blocks * 4096 bytes")
-    _check(_load().tetrt_probe_l1(buf.data_ptr(), buf.numel() * buf.element_size(), _PROBE[mode],
-                                  int(unit_bytes), int(units), int(blocks), int(iters), out.data_ptr(),
-                                  _stream(stream)))
 
 
 def tm_batch_create(max_jobs, max_rays):

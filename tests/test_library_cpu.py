@@ -153,10 +153,12 @@ def test_server_argument_errors(tetrt):
     assert lib.tm_server_free(None) == 0
 
 
-def test_probe_l1_argument_errors(tetrt):
-    """The calibration kernel's entry point rejects bad shapes before any launch
-    (the pointers below are never dereferenced)."""
-    L = tetrt.binding._load()
+def test_probe_l1_argument_errors():
+    """The calibration kernel's library (the benchmark's, apart from the
+    traversal library) rejects bad shapes before any launch (the pointers below
+    are never dereferenced)."""
+    from bench import probe_lib
+    L = probe_lib()
     buf, out = C.c_void_p(4096), C.c_void_p(8192)
     bad = [
         (buf, 1 << 20, 7, 128, 128, 16, 16, out),        # unknown mode
@@ -168,5 +170,11 @@ def test_probe_l1_argument_errors(tetrt):
         (None, 1 << 20, 0, 128, 128, 16, 16, out),       # NULL buffer
     ]
     for a in bad:
-        assert L.tetrt_probe_l1(*a, None) == -1, a   # TM_ERR_ARG
-        assert "tetrt_probe_l1" in tetrt.tm_last_error()
+        assert L.tetrt_probe_l1(*a, None) == -1, a
+        assert b"tetrt_probe_l1" in L.tetrt_probe_last_error()
+
+
+def test_probe_not_in_traversal_library(tetrt):
+    """The calibration kernel ships only in the benchmark's library."""
+    lib = C.CDLL(tetrt.library_path())
+    assert not hasattr(lib, "tetrt_probe_l1")
