@@ -34,12 +34,21 @@
  *
  * Per-ray result codes in out_tri: >= 0 triangle id, -1 miss, -3 invalid ray
  * or origin outside the mesh, -4 the mesh violated the face-connected chain
- * invariant during the walk.  A straight line enters each tet at most once, so
- * a walk longer than T steps can only be circling on a degenerate ray (one
- * running along a tet edge, whose endpoints both project onto the 2-D origin
- * and leave Algorithm 1 with zero determinants); such a ray takes the plain
- * definition instead -- the closest of all constrained triangles it meets
- * (Moller-Trumbore, inclusive edges) -- and reports steps = -1.
+ * invariant during the walk.
+ *
+ * Degenerate rays.  In exact arithmetic every face the walk keeps contains the
+ * ray: its projection holds the 2-D origin (all three edge determinants
+ * det(q_i, q_i+1) of the counter-clockwise face are >= 0).  In floating point
+ * this can only break where Algorithm 1 meets a zero determinant decided by
+ * rounding: a mesh vertex lies on the ray (a ray through a vertex, or running
+ * along a tet edge, whose endpoints both project onto the 2-D origin).  The
+ * walk may then circle, or leave the ray altogether and end on a face the ray
+ * never meets.  Both are detected -- a walk longer than T steps (a straight
+ * line enters each tet at most once), or a kept face whose projection misses
+ * the origin by more than rounding can explain (an edge determinant below
+ * -1e-9 E (|q_i|_1 + |q_i+1|_1), E the extent of the mesh) -- and such a ray
+ * takes the plain definition instead: the closest of all constrained
+ * triangles it meets (Moller-Trumbore, inclusive edges), with steps = -1.
  *
  * Build: cc -O2 -ffp-contract=off -fPIC -shared walk.c -o liboracle.so -lm
  */
@@ -62,6 +71,7 @@ static v3 vcross(v3 a, v3 b) {
 
 typedef struct {
     int64_t np, nt, ntri;
+    double extent;       /* largest side of the points' bounding box */
     const float* pts;
     const int32_t* tets;
     const int32_t* nbrs;
@@ -91,6 +101,15 @@ void* oracle_mesh_new(const float* pts, int64_t np, const int32_t* tets,
     omesh* m = (omesh*)calloc(1, sizeof(omesh));
     if (!m) return NULL;
     m->np = np; m->nt = nt; m->pts = pts; m->tets = tets; m->nbrs = nbrs; m->cflag = cflag;
+    for (int a = 0; a < 3; ++a) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int64_t i = 0; i < np; ++i) {
+            double c = (double)pts[3 * i + a];
+            if (c < lo) lo = c;
+            if (c > hi) hi = c;
+        }
+        if (np > 0 && hi - lo > m->extent) m->extent = hi - lo;
+    }
     m->face_tri = (int32_t*)malloc(sizeof(int32_t) * 4 * (size_t)(nt > 0 ? nt : 1));
     int64_t nflag = 0;
     for (int64_t k = 0; k < 4 * nt; ++k) { m->face_tri[k] = -1; nflag += cflag[k] != 0; }
@@ -169,6 +188,18 @@ static int get_exit_face(const double q[4][2]) {
         return 0;
     }
     if (det2(q[3], q[1]) < 0.0) return 2;
+    return 0;
+}
+
+/* Whether the kept face q[0..2] (counter-clockwise) misses the 2-D origin by
+ * more than rounding can explain: the walk has left the ray (see the header). */
+static int face_misses_ray(const double q[4][2], double extent) {
+    for (int i = 0; i < 3; ++i) {
+        const double* a = q[i];
+        const double* b = q[(i + 1) % 3];
+        double tol = 1e-9 * extent * (fabs(a[0]) + fabs(a[1]) + fabs(b[0]) + fabs(b[1]));
+        if (det2(a, b) < -tol) return 1;
+    }
     return 0;
 }
 
@@ -459,6 +490,11 @@ int oracle_trace(void* h, int64_t n, const float* orig, const float* dir, const 
             nxt = m->nbrs[4 * (int64_t)tet + j];
             cons = m->cflag[4 * (int64_t)tet + j] != 0;
             a[e] = id3; q[e][0] = q[3][0]; q[e][1] = q[3][1];
+            if (face_misses_ray(q, m->extent)) {
+                code = closest_by_definition(m, &F, tm, sf, &tt, bary, tets2);
+                steps = -1;
+                goto done;
+            }
         }
 
         if (code >= 0) {

@@ -155,6 +155,9 @@ def _check_vs_brute(om, points, orig, dirs, tmax=None, start_face=None, t_rtol=1
     r = om.trace(orig, dirs, tmax, start_face=start_face)
     bt, btt, bb = oracle.brute_closest_hit(points, om.tri_verts, orig, dirs, tmax, exclude=start_face)
     assert np.all(r["tri"] >= -1), np.unique(r["tri"])
+    # generic rays (no vertex on the ray) never need the fallback: the walk itself
+    # answers them
+    assert np.all(r["steps"] >= 0), np.nonzero(r["steps"] < 0)[0][:10]
     same = r["tri"] == bt
     # ties between triangles sharing an edge may go either way; the brute force
     # then has a second hit at the same t
@@ -256,6 +259,66 @@ def test_fallback_vs_brute_degenerate_rays(tiny_mesh, tiny_oracle, kind):
     same = ok & (w["tri"] == r["tri"])
     assert same.sum() > 0.95 * ok.sum()
     assert np.array_equal(w["tets"][same], r["tets"][same])
+
+
+@pytest.fixture(scope="module")
+def degenerate_set(tiny_mesh, tiny_oracle):
+    """The rays of the precision stress set (200,000 at seed 4) aimed through mesh
+    vertices and along tet edges, their walk results and brute force."""
+    m = tiny_mesh
+    o, d, k = precision_rays(m.points, m.tets, m.cflag, n=200_000, seed=4)
+    s = k >= 1
+    o, d, k = o[s], d[s], k[s]
+    w = tiny_oracle.trace(o, d)
+    b = oracle.brute_closest_hit(m.points, tiny_oracle.tri_verts, o, d)
+    return o, d, k, w, b
+
+
+def test_degenerate_rays_hits_lie_on_the_ray(tiny_mesh, tiny_oracle, degenerate_set):
+    """Every hit the oracle reports lies on its ray: the line meets the reported
+    triangle (to 1e-9 of the scene extent) at the reported t > 0, and no hit comes
+    before the closest one of the definition.  Rays that run along tet edges or
+    through vertices are where the FP64 walk meets zero determinants; a walk that
+    leaves its ray there must take the definition instead."""
+    from oracle.compare import ray_triangle_gap
+    o, d, k, w, (bt, btt, _) = degenerate_set
+    h = np.nonzero(w["tri"] >= 0)[0]
+    gap = ray_triangle_gap(tiny_mesh.points, tiny_oracle.tri_verts, w["tri"][h], o[h], d[h])
+    assert gap.max() <= 1e-9, (gap.max(), h[np.argmax(gap)])
+    assert np.all(w["t"][h] > 0)
+    both = h[bt[h] >= 0]
+    assert np.all(w["t"][both] >= btt[both] * (1 - 1e-9))
+    # the degenerate rays do exercise the fallback (circling or leaving the ray)
+    assert (w["steps"] == -1).sum() > 100
+
+
+def test_degenerate_rays_vs_brute(tiny_mesh, tiny_oracle, degenerate_set):
+    """Against the definition: the same triangle, except where the ray meets the
+    surface at an edge or vertex (several triangles then contain the hit point, or
+    the walk may pass between them); t to 1e-12 and weights to 1e-9 on identical
+    hits."""
+    o, d, k, w, (bt, btt, bb) = degenerate_set
+    same = w["tri"] == bt
+    assert same.mean() > 0.999
+    P = tiny_mesh.points.astype(np.float64)
+    mism = np.nonzero(~same)[0]
+    hb = mism[bt[mism] >= 0]
+    if hb.size:
+        hp = o[hb].astype(np.float64) + btt[hb, None] * d[hb].astype(np.float64)
+        tv = tiny_oracle.tri_verts[bt[hb]]
+        A, B, Cc = P[tv[:, 0]], P[tv[:, 1]], P[tv[:, 2]]
+
+        def seg(p, a, b):
+            ab = b - a
+            t = np.clip(np.einsum("ij,ij->i", p - a, ab) / np.einsum("ij,ij->i", ab, ab), 0, 1)
+            return np.linalg.norm(p - (a + t[:, None] * ab), axis=1)
+
+        edge = np.minimum(np.minimum(seg(hp, A, B), seg(hp, B, Cc)), seg(hp, Cc, A))
+        assert edge.max() <= 1e-9, (edge.max(), hb[np.argmax(edge)])
+    h = same & (bt >= 0)
+    assert h.sum() > 1000
+    assert np.all(np.abs(w["t"][h] - btt[h]) <= 1e-12 * np.abs(btt[h]) + 1e-12)
+    assert np.all(np.abs(w["bary"][h] - bb[h]) <= 1e-9)
 
 
 def test_fallback_vs_brute_secondary(tiny_mesh, tiny_oracle):

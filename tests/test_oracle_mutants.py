@@ -37,6 +37,10 @@ MUTANTS = {
     "fallback_hit_behind_origin": ("!(t > 0.0) || t > tm", "!(t > -1e-3) || t > tm"),
     "fallback_front_back_swapped": ("tets2[0] = ta_ahead ? tb : ta;", "tets2[0] = ta_ahead ? ta : tb;"),
     "walk_front_back_swapped": ("tets2[0] = cur; tets2[1] = nxt;", "tets2[0] = nxt; tets2[1] = cur;"),
+    # a walk that leaves its ray (a vertex on the ray, zero determinants decided by
+    # rounding) must be caught and answered by the definition
+    "lost_walk_not_caught": ("if (face_misses_ray(q, m->extent)) {", "if (0) {"),
+    "lost_walk_test_sign": ("if (det2(a, b) < -tol) return 1;", "if (det2(b, a) < -tol) return 1;"),
     "ccw_not_enforced": ("            if (o2 < 0.0) {\n                int32_t ti = a[1]; a[1] = a[2]; a[2] = ti;\n                double t0 = q[1][0], t1 = q[1][1];\n                q[1][0] = q[2][0]; q[1][1] = q[2][1]; q[2][0] = t0; q[2][1] = t1;\n            }\n            nxt = start;",
                          "            nxt = start;"),
 }
