@@ -25,7 +25,11 @@
  *     otherwise).
  *   - Work is enqueued on the given HIP stream (NULL = the default stream) and
  *     returns without synchronising.  A handle is read-only after upload, so
- *     traces on different streams may run concurrently.
+ *     traces on different streams may run concurrently; traces that bin through
+ *     the handle's own workspace are ordered one after another (a trace on
+ *     another stream than the previous such trace waits for it on the device).
+ *   - trace_closest, tetmesh_locate, tetmesh_bin_rays and the batch launches
+ *     never allocate memory or wait for the device.
  *   - Return value: TM_OK, or a negative TM_ERR_* code; tm_last_error() then
  *     describes the first problem found (per calling thread).
  */
@@ -61,16 +65,24 @@ enum {
     TM_LAYOUT_TET16 = 1, /* xor of the four vertex ids + three neighbour fields each
                             xored with the fourth; the walk decodes the next tet from
                             the previous one (16 B/tet) */
-    TM_LAYOUT_TET32N = 2 /* not a layout of the paper: the four neighbour fields + the
+    TM_LAYOUT_TET32N = 2, /* not a layout of the paper: the four neighbour fields + the
                             xor-sum of each neighbour (32 B/tet), so a walk step loads
                             its record and its point together */
+    TM_LAYOUT_TET32 = 3  /* the paper's Tet32 (Fig. 2): three vertex ids, the xor of all
+                            four, and the four neighbour fields, N_j across V_j (32 B/tet);
+                            the next tet is found by comparing the exit vertex with the
+                            stored ids (Algorithms 2-3) */
 };
 
 /* memory order of points and tets (paper, Sec. "Reordering tetrahedral mesh data") */
 enum {
     TM_SFC_HILBERT = 0, /* points by position, tets by centroid, 3-D Hilbert key */
     TM_SFC_MORTON = 1,  /* same keys on the Morton (Z-order) curve */
-    TM_SFC_NONE = 2     /* keep the caller's order */
+    TM_SFC_NONE = 2,    /* keep the caller's order */
+    TM_SFC_HILBERT_REGIONS = 3 /* tets grouped by region first (tets that constrained faces
+                            enclose together, which no walk leaves), regions in the
+                            Hilbert order of their first tet, Hilbert order inside a
+                            region; points as TM_SFC_HILBERT */
 };
 
 typedef struct tm_mesh_s* tm_mesh;
@@ -82,6 +94,10 @@ typedef struct {
     int32_t sfc;       /* TM_SFC_* */
     int32_t validate;  /* 1 = check the mesh before packing (recommended) */
     int32_t seed_grid; /* cells per axis of the point-location seed grid; 0 = automatic */
+    int64_t bin_rays;  /* rays the handle's own binning workspace holds (4 bytes each),
+                          allocated here, once; 0 = none.  trace_closest bins through it
+                          when the caller passes no workspace of its own.  0 <= bin_rays
+                          < 2^31 */
 } tm_upload_opts;
 
 /* Sizes of an uploaded mesh (tetmesh_info). */
@@ -94,7 +110,7 @@ typedef struct {
     int32_t layout;
     int32_t sfc;
     int32_t seed_grid;
-    int32_t reserved;
+    int32_t n_regions;   /* TM_SFC_HILBERT_REGIONS: regions found at upload (else 0) */
 } tm_info;
 
 /* Options for trace_closest; pass NULL for the defaults (all fields 0). */
@@ -132,10 +148,12 @@ typedef struct {
                             and determinants in float64 from the float32 points, basis and
                             origin; the start tet's exit face is then also found in float64.
                             With the scene extent 1, eps >= 1e-6 covers float32 rounding */
-    void* workspace;     /* device scratch for binning, or NULL: the handle then uses (and
-                            grows) a workspace of its own, so binned traces on one handle
-                            must not overlap in time unless each passes its own */
-    int64_t workspace_bytes; /* size of workspace (tetmesh_trace_workspace gives the need) */
+    void* workspace;     /* device scratch for binning (tetmesh_trace_workspace gives the
+                            need), or NULL: the handle's own workspace (tm_upload_opts.bin_rays)
+                            is then used when it is large enough.  A binned trace with
+                            neither: sort = 2 fails (TM_ERR_ARG), sort = 0 traces the rays
+                            unbinned (the same results) */
+    int64_t workspace_bytes; /* size of workspace */
     int32_t* fp64_steps; /* device int32 [n_rays] or NULL: out: walk steps decided in float64
                             (0 when eps = 0) */
     const int32_t* order; /* device int32 [n_rays] or NULL: trace the rays in this order (lane j
@@ -168,7 +186,7 @@ typedef struct {
  *                                      set on both sides of an interior face
  *   opts     host, nullable
  *   out      host; receives the handle (owns all device memory until tetmesh_free)
- * Limits: 1 <= n_tets <= 214,748,364 (134,217,727 with TM_LAYOUT_TET32N: the
+ * Limits: 1 <= n_tets <= 214,748,364 (134,217,727 with TM_LAYOUT_TET32N or _TET32: the
  * records and points stay below 4 GiB each), 4 <= n_points <= 357,913,941, fewer
  * than 2^31 - 1 constrained triangles.  Inputs are copied; the caller may free them on return.
  * Errors: TM_ERR_ARG, TM_ERR_MESH (with validate = 1: vertex id out of range,

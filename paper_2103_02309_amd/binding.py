@@ -14,8 +14,8 @@ _LIB_PATH = os.path.join(_HERE, "libtetrt.so")
 
 TM_OK, TM_ERR_ARG, TM_ERR_MESH, TM_ERR_OOM, TM_ERR_HIP = 0, -1, -2, -3, -4
 RAY_MISS, RAY_STEP_CAP, RAY_INVALID = -1, -2, -3
-_LAYOUTS = {"tet20": 0, "tet16": 1, "tet32n": 2}
-_SFC = {"hilbert": 0, "morton": 1, "none": 2}
+_LAYOUTS = {"tet20": 0, "tet16": 1, "tet32n": 2, "tet32": 3}
+_SFC = {"hilbert": 0, "morton": 1, "none": 2, "hilbert_regions": 3}
 
 
 class TetRTError(RuntimeError):
@@ -26,7 +26,7 @@ class TetRTError(RuntimeError):
 
 class _UploadOpts(C.Structure):
     _fields_ = [("layout", C.c_int32), ("sfc", C.c_int32), ("validate", C.c_int32),
-                ("seed_grid", C.c_int32)]
+                ("seed_grid", C.c_int32), ("bin_rays", C.c_int64)]
 
 
 class _TraceOpts(C.Structure):
@@ -92,7 +92,7 @@ _KINDS = {"primary": 0, "shadow": 1, "ao": 2}
 class _Info(C.Structure):
     _fields_ = [("n_tets", C.c_int64), ("n_points", C.c_int64), ("n_tris", C.c_int64),
                 ("hot_bytes", C.c_int64), ("cold_bytes", C.c_int64), ("layout", C.c_int32),
-                ("sfc", C.c_int32), ("seed_grid", C.c_int32), ("reserved", C.c_int32)]
+                ("sfc", C.c_int32), ("seed_grid", C.c_int32), ("n_regions", C.c_int32)]
 
 
 _lib = None
@@ -205,8 +205,9 @@ def _stream(stream):
 # ---- the C-ABI, one function per entry point ---------------------------------------
 
 def tetmesh_upload(points, tets, nbrs, cflag, layout="tet20", sfc="hilbert", validate=True,
-                   seed_grid=0):
-    """Pack and upload a mesh (host arrays); returns the raw handle (int)."""
+                   seed_grid=0, bin_rays=0):
+    """Pack and upload a mesh (host arrays); returns the raw handle (int).  ``bin_rays``:
+    rays the handle's own binning workspace holds (allocated here; 0 = none)."""
     L = _load()
     P = _host(points, np.float32, (3,), "points")
     T = _host(tets, np.int32, (4,), "tets")
@@ -214,7 +215,7 @@ def tetmesh_upload(points, tets, nbrs, cflag, layout="tet20", sfc="hilbert", val
     F = _host(cflag, np.uint8, (4,), "cflag")
     if N.shape != T.shape or F.shape != T.shape:
         raise ValueError("tets, nbrs and cflag must have the same shape")
-    opts = _UploadOpts(_LAYOUTS[layout], _SFC[sfc], int(bool(validate)), int(seed_grid))
+    opts = _UploadOpts(_LAYOUTS[layout], _SFC[sfc], int(bool(validate)), int(seed_grid), int(bin_rays))
     h = C.c_void_p()
     _check(L.tetmesh_upload(P.ctypes.data, P.shape[0], T.ctypes.data, N.ctypes.data, F.ctypes.data,
                             T.shape[0], C.byref(opts), C.byref(h)))
@@ -275,7 +276,7 @@ def tetmesh_tri_vertices(handle, tri):
 def tetmesh_info(handle):
     info = _Info()
     _check(_load().tetmesh_info(C.c_void_p(handle), C.byref(info)))
-    return {k: getattr(info, k) for k, _ in _Info._fields_ if k != "reserved"}
+    return {k: getattr(info, k) for k, _ in _Info._fields_}
 
 
 def tetmesh_free(handle):
@@ -466,6 +467,16 @@ class Mesh:
 
     def trace_into(self, out, orig, dirs, tmax=None, start_tet=None, start_face=None,
                    workspace=None, stream=None, **opts):
+        """Trace into caller tensors.  A trace that bins its rays (``sort``) without a
+        ``workspace`` gets one from torch's allocator here, held on the stream it runs
+        on, so the library itself never allocates."""
+        if workspace is None and opts.get("order") is None:
+            wo = {k: v for k, v in opts.items() if k in _TRACE_KEYS}
+            need = self.workspace_bytes(int(orig.shape[0]), tmax is not None, **wo)
+            if need > 0:
+                workspace = torch.empty(need, dtype=torch.uint8, device=orig.device)
+                if stream is not None and stream != torch.cuda.current_stream(orig.device):
+                    workspace.record_stream(stream)
         trace_closest(self.handle, orig, dirs, out["tri"], out["t"], out["bary"], tmax=tmax,
                       start_tet=start_tet, start_face=start_face, hit_tets=out.get("hit_tets"),
                       steps=out.get("steps"), workspace=workspace,

@@ -80,7 +80,8 @@ int check_device(const tm_mesh_s* m, const char* what) {
 void release(tm_mesh_s* m) {
     for (void* p : m->allocations) (void)hipFree(p);
     m->allocations.clear();
-    if (m->ws) (void)hipFree(m->ws);
+    if (m->ws_done) (void)hipEventDestroy(m->ws_done);
+    m->ws_done = nullptr;
     m->ws = nullptr;
     m->ws_bytes = 0;
 }
@@ -107,6 +108,141 @@ int upload_array(tm_mesh_s* m, const std::vector<T>& v, const T** out, int64_t* 
 
 }  // namespace
 
+namespace tetrt {
+
+int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d_dir,
+               const float* d_tmax, const int32_t* d_start_tet, const int32_t* d_start_face,
+               int32_t* d_tri, float* d_t, float* d_bary, int32_t* d_hit_tets, int32_t* d_steps,
+               const tm_trace_opts* opts, void* hip_stream, void* fixed_ws, int64_t fixed_ws_bytes,
+               const char* name) {
+    if (!m) return fail(TM_ERR_ARG, "%s: NULL mesh", name);
+    if (int rc = check_device(m, name)) return rc;
+    if (n_rays < 0 || n_rays > int64_t(0x7FFFFFFF))
+        return fail(TM_ERR_ARG, "%s: n_rays = %lld out of range [0, 2^31)", name, (long long)n_rays);
+    if (n_rays == 0) return TM_OK;
+    if (!d_orig || !d_dir || !d_tri || !d_t || !d_bary)
+        return fail(TM_ERR_ARG, "%s: NULL required array", name);
+    if ((reinterpret_cast<uintptr_t>(d_bary) & 7) || (reinterpret_cast<uintptr_t>(d_hit_tets) & 7))
+        return fail(TM_ERR_ARG, "%s: bary / hit_tets must be 8-byte aligned", name);
+    tm_trace_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    if (o.max_steps < 0) return fail(TM_ERR_ARG, "%s: negative max_steps", name);
+    if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
+        return fail(TM_ERR_ARG, "%s: block must be 64, 128 or 256", name);
+    if (o.kernel < 0 || o.kernel > 2) return fail(TM_ERR_ARG, "%s: kernel must be 0, 1 or 2", name);
+    if (o.refill < 0 || o.refill > 64) return fail(TM_ERR_ARG, "%s: refill must be in [0, 64]", name);
+    if (o.grid_cap < 0) return fail(TM_ERR_ARG, "%s: negative grid_cap", name);
+    if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "%s: xcds must be in [0, 64]", name);
+    if (o.xcd_blocks < 0 || o.xcd_blocks > 65536)
+        return fail(TM_ERR_ARG, "%s: xcd_blocks must be in [0, 65536]", name);
+    if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "%s: sort must be 0, 1 or 2", name);
+    if (!(o.eps >= 0.0f) || !(o.eps < 1.0f)) return fail(TM_ERR_ARG, "%s: eps must be in [0, 1)", name);
+    if (o.eps > 0.0f && o.kernel == 2)
+        return fail(TM_ERR_ARG, "%s: the precision variant (eps > 0) runs one lane per ray", name);
+    if (o.workspace_bytes < 0 || (o.workspace_bytes > 0 && !o.workspace))
+        return fail(TM_ERR_ARG, "%s: bad workspace", name);
+    if (fixed_ws && o.workspace)
+        return fail(TM_ERR_ARG, "%s: takes no workspace (it bins through its own)", name);
+    SortCfg sc;
+    bool binned = false;
+    int rc = sort_config(m, o, n_rays, d_tmax != nullptr, &sc, &binned);
+    if (rc != TM_OK) return rc;
+    if (o.order) binned = false;   // the caller's order replaces the call's binning
+    const int64_t need = binned ? sort_workspace_bytes(n_rays) : 0;
+    // where the binning permutation goes: the given fixed workspace, the caller's,
+    // or the handle's own; with none of them large enough an explicit sort = 2
+    // is an error and the automatic choice traces the rays unbinned
+    void* ws = nullptr;
+    bool handle_ws = false;
+    if (binned) {
+        if (fixed_ws) {
+            if (fixed_ws_bytes < need)
+                return fail(TM_ERR_ARG, "%s: %lld rays to bin, at most %lld", name, (long long)n_rays,
+                            (long long)(fixed_ws_bytes / 4));
+            ws = fixed_ws;
+        } else if (o.workspace) {
+            if (o.workspace_bytes < need)
+                return fail(TM_ERR_ARG, "%s: workspace of %lld bytes, %lld needed", name,
+                            (long long)o.workspace_bytes, (long long)need);
+            ws = o.workspace;
+        } else if (m->ws_bytes >= need) {
+            ws = m->ws;
+            handle_ws = true;
+        } else if (o.sort == 2) {
+            return fail(TM_ERR_ARG, "%s: binning %lld rays needs a workspace of %lld bytes (opts.workspace, "
+                        "or tm_upload_opts.bin_rays >= n_rays)", name, (long long)n_rays, (long long)need);
+        } else {
+            binned = false;
+        }
+    }
+    RayArgs r;
+    r.perm = o.order;
+    r.orig = d_orig;
+    r.dir = d_dir;
+    r.tmax = d_tmax;
+    r.start_tet = d_start_tet;
+    r.start_face = d_start_face;
+    r.tri = d_tri;
+    r.t = d_t;
+    r.bary = d_bary;
+    r.hit_tets = d_hit_tets;
+    r.steps = d_steps;
+    r.fp64_steps = o.fp64_steps;
+    r.n = n_rays;
+    r.max_steps = o.max_steps > 0 ? o.max_steps : 65536;
+    LaunchCfg c;
+    // automatic: 256-thread blocks for binned (or caller-ordered) rays, 128 for
+    // the rest, whose walks differ more in length from lane to lane; smaller
+    // blocks retire sooner and even out the XCDs' loads (camera rays: 0.834 vs
+    // 0.853 ms; binned AO rays: 1.396 vs 1.340 ms)
+    c.block = o.block ? o.block : ((binned || o.order) ? 256 : 128);
+    c.cus = m->cus;
+    c.waves_per_simd = 8;
+    c.refill = o.refill ? o.refill : 16;
+    c.grid_cap = o.grid_cap;
+    // automatic: binned launches (their rays are ordered along the image, then by
+    // direction inside each chunk) give each XCD one contiguous range of blocks, so
+    // an XCD's L2 holds the tets of its part of the scene; unbinned launches keep
+    // the dispatcher's round-robin placement, which balances walks of uneven length
+    c.xcds = o.xcds ? o.xcds : ((binned || o.order) ? xcd_count(m->cus) : 1);
+    c.xcd_blocks = o.xcd_blocks;
+    // automatic: one lane per ray (the persistent-lane kernel is slower on every
+    // measured workload and runs only when asked for)
+    c.kernel = o.kernel ? o.kernel : 1;
+    c.eps = o.eps;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e;
+    std::unique_lock<std::mutex> lock(m->ws_mu, std::defer_lock);
+    if (binned) {
+        if (handle_ws) {
+            // the previous trace through the handle's workspace may still be reading
+            // its permutation on another stream: this stream waits for it (stream
+            // order covers the same stream)
+            lock.lock();
+            if (m->ws_used && m->ws_stream != stream) {
+                e = hipStreamWaitEvent(stream, m->ws_done, 0);
+                if (e != hipSuccess) return hip_fail(e, name);
+            }
+        }
+        int32_t* perm = nullptr;
+        e = launch_sort(sc, d_orig, d_dir, n_rays, ws, &perm, stream);
+        if (e != hipSuccess) return hip_fail(e, "ray binning launch");
+        r.perm = perm;
+    }
+    e = launch_trace(m->dev, r, c, stream);
+    if (e != hipSuccess) return hip_fail(e, "trace kernel launch");
+    if (handle_ws) {
+        e = hipEventRecord(m->ws_done, stream);
+        if (e != hipSuccess) return hip_fail(e, name);
+        m->ws_stream = stream;
+        m->ws_used = true;
+    }
+    return TM_OK;
+}
+
+}  // namespace tetrt
+
 extern "C" {
 
 const char* tm_last_error(void) { return tetrt::last_error(); }
@@ -127,16 +263,20 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     // records and points below 4 GiB each: the sizes the packer's index arithmetic
     // is written for
     {
-        const int64_t rb = (opts && opts->layout == TM_LAYOUT_TET32N) ? 32 : 20;
+        const int64_t rb = (opts && (opts->layout == TM_LAYOUT_TET32N || opts->layout == TM_LAYOUT_TET32)) ? 32 : 20;
         if (n_tets * rb > int64_t(0xFFFFFFFFLL) || n_points * 12 > int64_t(0xFFFFFFFFLL))
             return fail(TM_ERR_ARG, "tetmesh_upload: mesh too large (at most %lld tets and %lld points)",
                         (long long)(0xFFFFFFFFLL / rb), (long long)(0xFFFFFFFFLL / 12));
     }
-    tm_upload_opts o = {TM_LAYOUT_TET20, TM_SFC_HILBERT, 1, 0};
+    tm_upload_opts o = {TM_LAYOUT_TET20, TM_SFC_HILBERT, 1, 0, 0};
     if (opts) o = *opts;
-    if (o.layout != TM_LAYOUT_TET20 && o.layout != TM_LAYOUT_TET16 && o.layout != TM_LAYOUT_TET32N)
+    if (o.bin_rays < 0 || o.bin_rays > int64_t(0x7FFFFFFF))
+        return fail(TM_ERR_ARG, "tetmesh_upload: bin_rays = %lld out of range [0, 2^31)",
+                    (long long)o.bin_rays);
+    if (o.layout != TM_LAYOUT_TET20 && o.layout != TM_LAYOUT_TET16 && o.layout != TM_LAYOUT_TET32N &&
+        o.layout != TM_LAYOUT_TET32)
         return fail(TM_ERR_ARG, "tetmesh_upload: unsupported layout %d", o.layout);
-    if (o.sfc < TM_SFC_HILBERT || o.sfc > TM_SFC_NONE)
+    if (o.sfc < TM_SFC_HILBERT || o.sfc > TM_SFC_HILBERT_REGIONS)
         return fail(TM_ERR_ARG, "tetmesh_upload: unknown sfc %d", o.sfc);
     if (o.seed_grid < 0 || o.seed_grid > 256)
         return fail(TM_ERR_ARG, "tetmesh_upload: seed_grid %d out of range [0, 256]", o.seed_grid);
@@ -164,6 +304,7 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     m->ntri = pm.ntri;
     m->layout = pm.layout;
     m->sfc = pm.sfc;
+    m->n_regions = pm.n_regions;
     int64_t hot = 0, cold = 0;
     tetrt::DevMesh& d = m->dev;
     if ((rc = upload_array(m, pm.rec, &d.rec, &hot)) ||
@@ -178,6 +319,28 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
         release(m);
         delete m;
         return rc;
+    }
+    if (o.bin_rays > 0) {
+        // the handle's binning workspace, allocated once here (traces never allocate)
+        const int64_t need = tetrt::sort_workspace_bytes(o.bin_rays);
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, size_t(need));
+        if (e == hipSuccess) {
+            m->allocations.push_back(p);
+            e = hipEventCreateWithFlags(&m->ws_done, hipEventDisableTiming);
+        } else {
+            (void)hipGetLastError();
+        }
+        if (e != hipSuccess) {
+            release(m);
+            delete m;
+            return fail(e == hipErrorOutOfMemory ? TM_ERR_OOM : TM_ERR_HIP,
+                        "tetmesh_upload: binning workspace of %lld bytes: %s", (long long)need,
+                        hipGetErrorString(e));
+        }
+        m->ws = p;
+        m->ws_bytes = need;
+        cold += need;
     }
     for (int a = 0; a < 3; ++a) {
         d.lo[a] = pm.lo[a];
@@ -209,116 +372,8 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
                   int32_t* d_tri, float* d_t, float* d_bary, int32_t* d_hit_tets, int32_t* d_steps,
                   const tm_trace_opts* opts, void* hip_stream) {
     tetrt::clear_error();
-    if (!m) return fail(TM_ERR_ARG, "trace_closest: NULL mesh");
-    if (int rc = check_device(m, "trace_closest")) return rc;
-    if (n_rays < 0 || n_rays > int64_t(0x7FFFFFFF))
-        return fail(TM_ERR_ARG, "trace_closest: n_rays = %lld out of range [0, 2^31)",
-                    (long long)n_rays);
-    if (n_rays == 0) return TM_OK;
-    if (!d_orig || !d_dir || !d_tri || !d_t || !d_bary)
-        return fail(TM_ERR_ARG, "trace_closest: NULL required array");
-    if ((reinterpret_cast<uintptr_t>(d_bary) & 7) || (reinterpret_cast<uintptr_t>(d_hit_tets) & 7))
-        return fail(TM_ERR_ARG, "trace_closest: bary / hit_tets must be 8-byte aligned");
-    tm_trace_opts o;
-    std::memset(&o, 0, sizeof o);
-    if (opts) o = *opts;
-    if (o.max_steps < 0) return fail(TM_ERR_ARG, "trace_closest: negative max_steps");
-    if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
-        return fail(TM_ERR_ARG, "trace_closest: block must be 64, 128 or 256");
-    if (o.kernel < 0 || o.kernel > 2) return fail(TM_ERR_ARG, "trace_closest: kernel must be 0, 1 or 2");
-    if (o.refill < 0 || o.refill > 64) return fail(TM_ERR_ARG, "trace_closest: refill must be in [0, 64]");
-    if (o.grid_cap < 0) return fail(TM_ERR_ARG, "trace_closest: negative grid_cap");
-    if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "trace_closest: xcds must be in [0, 64]");
-    if (o.xcd_blocks < 0 || o.xcd_blocks > 65536)
-        return fail(TM_ERR_ARG, "trace_closest: xcd_blocks must be in [0, 65536]");
-    if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "trace_closest: sort must be 0, 1 or 2");
-    if (!(o.eps >= 0.0f) || !(o.eps < 1.0f))
-        return fail(TM_ERR_ARG, "trace_closest: eps must be in [0, 1)");
-    if (o.eps > 0.0f && o.kernel == 2)
-        return fail(TM_ERR_ARG, "trace_closest: the precision variant (eps > 0) runs one lane per ray");
-    if (o.workspace_bytes < 0 || (o.workspace_bytes > 0 && !o.workspace))
-        return fail(TM_ERR_ARG, "trace_closest: bad workspace");
-    tetrt::SortCfg sc;
-    bool binned = false;
-    int rc = sort_config(m, o, n_rays, d_tmax != nullptr, &sc, &binned);
-    if (rc != TM_OK) return rc;
-    if (o.order) binned = false;   // the caller's order replaces the call's binning
-    tetrt::RayArgs r;
-    r.perm = o.order;
-    r.orig = d_orig;
-    r.dir = d_dir;
-    r.tmax = d_tmax;
-    r.start_tet = d_start_tet;
-    r.start_face = d_start_face;
-    r.tri = d_tri;
-    r.t = d_t;
-    r.bary = d_bary;
-    r.hit_tets = d_hit_tets;
-    r.steps = d_steps;
-    r.fp64_steps = o.fp64_steps;
-    r.n = n_rays;
-    r.max_steps = o.max_steps > 0 ? o.max_steps : 65536;
-    tetrt::LaunchCfg c;
-    // automatic: 256-thread blocks for binned (or caller-ordered) rays, 128 for
-    // the rest, whose walks differ more in length from lane to lane; smaller
-    // blocks retire sooner and even out the XCDs' loads (camera rays: 0.834 vs
-    // 0.853 ms; binned AO rays: 1.396 vs 1.340 ms)
-    c.block = o.block ? o.block : ((binned || o.order) ? 256 : 128);
-    c.cus = m->cus;
-    c.waves_per_simd = 8;
-    c.refill = o.refill ? o.refill : 16;
-    c.grid_cap = o.grid_cap;
-    // automatic: binned launches (their rays are ordered along the image, then by
-    // direction inside each chunk) give each XCD one contiguous range of blocks, so
-    // an XCD's L2 holds the tets of its part of the scene; unbinned launches keep
-    // the dispatcher's round-robin placement, which balances walks of uneven length
-    c.xcds = o.xcds ? o.xcds : ((binned || o.order) ? tetrt::xcd_count(m->cus) : 1);
-    c.xcd_blocks = o.xcd_blocks;
-    // automatic: one lane per ray (the persistent-lane kernel is slower on every
-    // measured workload and runs only when asked for)
-    c.kernel = o.kernel ? o.kernel : 1;
-    c.eps = o.eps;
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    hipError_t e;
-    if (binned) {
-        // bin the rays, then trace them in bin order through the permutation
-        const int64_t need = tetrt::sort_workspace_bytes(n_rays);
-        void* ws = o.workspace;
-        std::unique_lock<std::mutex> lock(m->ws_mu, std::defer_lock);
-        if (ws) {
-            if (o.workspace_bytes < need)
-                return fail(TM_ERR_ARG, "trace_closest: workspace of %lld bytes, %lld needed",
-                            (long long)o.workspace_bytes, (long long)need);
-        } else {
-            lock.lock();
-            if (m->ws_bytes < need) {
-                // grow the handle's workspace once; earlier work using it must end first
-                if (m->ws) {
-                    e = hipDeviceSynchronize();
-                    if (e != hipSuccess) return hip_fail(e, "trace_closest: synchronize");
-                    (void)hipFree(m->ws);
-                    m->ws = nullptr;
-                    m->ws_bytes = 0;
-                }
-                e = hipMalloc(&m->ws, size_t(need));
-                if (e != hipSuccess) {
-                    (void)hipGetLastError();
-                    m->ws = nullptr;
-                    return fail(TM_ERR_OOM, "trace_closest: workspace of %lld bytes: %s", (long long)need,
-                                hipGetErrorString(e));
-                }
-                m->ws_bytes = need;
-            }
-            ws = m->ws;
-        }
-        int32_t* perm = nullptr;
-        e = tetrt::launch_sort(sc, d_orig, d_dir, n_rays, ws, &perm, stream);
-        if (e != hipSuccess) return hip_fail(e, "trace_closest: ray binning launch");
-        r.perm = perm;
-    }
-    e = tetrt::launch_trace(m->dev, r, c, stream);
-    if (e != hipSuccess) return hip_fail(e, "trace_closest: kernel launch");
-    return TM_OK;
+    return tetrt::trace_impl(m, n_rays, d_orig, d_dir, d_tmax, d_start_tet, d_start_face, d_tri, d_t,
+                             d_bary, d_hit_tets, d_steps, opts, hip_stream, nullptr, 0, "trace_closest");
 }
 
 int tetmesh_bin_rays(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d_dir,
@@ -400,7 +455,7 @@ int tetmesh_info(tm_mesh m, tm_info* out) {
     out->layout = m->layout;
     out->sfc = m->sfc;
     out->seed_grid = m->dev.G;
-    out->reserved = 0;
+    out->n_regions = int32_t(m->n_regions);
     return TM_OK;
 }
 

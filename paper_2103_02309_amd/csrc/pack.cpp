@@ -141,6 +141,32 @@ std::string check_tet(int64_t t, int64_t np, int64_t nt, const float* P, const i
     return std::string();
 }
 
+// Region label of every tet (caller numbering): tets joined across faces that
+// are neither constrained nor on the boundary share a label (the smallest tet
+// id of their component).  Union-find with path halving.
+std::vector<int32_t> tet_regions(const int32_t* nbrs, const uint8_t* cflag, int64_t nt) {
+    std::vector<int32_t> parent(static_cast<size_t>(nt));
+    for (int64_t t = 0; t < nt; ++t) parent[size_t(t)] = int32_t(t);
+    auto find = [&parent](int32_t x) {
+        while (parent[size_t(x)] != x) {
+            parent[size_t(x)] = parent[size_t(parent[size_t(x)])];
+            x = parent[size_t(x)];
+        }
+        return x;
+    };
+    for (int64_t t = 0; t < nt; ++t)
+        for (int j = 0; j < 4; ++j) {
+            const int32_t nb = nbrs[4 * t + j];
+            if (nb < 0 || nb <= t || cflag[4 * t + j]) continue;
+            int32_t a = find(int32_t(t)), b = find(nb);
+            if (a == b) continue;
+            if (a < b) std::swap(a, b);
+            parent[size_t(a)] = b;
+        }
+    for (int64_t t = 0; t < nt; ++t) parent[size_t(t)] = find(int32_t(t));
+    return parent;
+}
+
 inline uint64_t spread3(uint32_t x, int bits) {
     uint64_t r = 0;
     for (int b = 0; b < bits; ++b) r |= uint64_t((x >> b) & 1u) << (3 * b);
@@ -305,9 +331,34 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
             }
         });
         parallel_sort(kt);
-        for (int64_t i = 0; i < nt; ++i) {
-            M.t_new2old[i] = int32_t(kt[i].id);
-            M.t_old2new[kt[i].id] = int32_t(i);
+        if (opts.sfc == TM_SFC_HILBERT_REGIONS) {
+            // Regions first (paper, Sec. "Reordering tetrahedral mesh data"): the
+            // tets that constrained faces enclose together -- a walk never leaves
+            // its region -- are stored contiguously, regions in the curve order of
+            // their first tet, and tets inside a region in curve order.  Region
+            // labels: components of the face-adjacency graph without its
+            // constrained faces.
+            std::vector<int32_t> region = tet_regions(nbrs, cflag, nt);
+            std::vector<int32_t> rank(size_t(nt), -1);   // region label -> rank
+            int32_t nreg = 0;
+            for (int64_t i = 0; i < nt; ++i) {
+                int32_t& r = rank[size_t(region[kt[i].id])];
+                if (r < 0) r = nreg++;
+            }
+            std::vector<int64_t> start(size_t(nreg) + 1, 0);
+            for (int64_t i = 0; i < nt; ++i) ++start[size_t(rank[size_t(region[kt[i].id])]) + 1];
+            for (int32_t r = 0; r < nreg; ++r) start[size_t(r) + 1] += start[size_t(r)];
+            for (int64_t i = 0; i < nt; ++i) {   // stable: curve order inside a region
+                const int64_t pos = start[size_t(rank[size_t(region[kt[i].id])])]++;
+                M.t_new2old[pos] = int32_t(kt[i].id);
+            }
+            for (int64_t i = 0; i < nt; ++i) M.t_old2new[M.t_new2old[i]] = int32_t(i);
+            M.n_regions = nreg;
+        } else {
+            for (int64_t i = 0; i < nt; ++i) {
+                M.t_new2old[i] = int32_t(kt[i].id);
+                M.t_old2new[kt[i].id] = int32_t(i);
+            }
         }
     }
 
@@ -320,10 +371,11 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
         M.pts[3 * i + 2] = s[2];
     }
 
-    // ---- tet records (Tet20, Tet16 or Tet32N) ------------------------------
+    // ---- tet records (Tet20, Tet16, Tet32 or Tet32N) -----------------------
     const bool t16 = opts.layout == TM_LAYOUT_TET16;
     const bool t32n = opts.layout == TM_LAYOUT_TET32N;
-    M.rec.resize(size_t((t16 ? 4 : (t32n ? 8 : 5)) * nt));
+    const bool t32 = opts.layout == TM_LAYOUT_TET32;
+    M.rec.resize(size_t((t16 ? 4 : ((t32n || t32) ? 8 : 5)) * nt));
     if (t16) M.n3.resize(size_t(nt));
     M.tetv.resize(size_t(4 * nt));
     std::vector<int32_t> vx_of(nt);   // xor field of every (new) tet
@@ -372,6 +424,12 @@ int pack_mesh(const float* P, int64_t np, const int32_t* tets, const int32_t* nb
                     M.rec[8 * tn + r] = int32_t(field[r]);
                     M.rec[8 * tn + 4 + r] = nvx[r];
                 }
+            } else if (t32) {
+                // Fig. 2: V0, V1, V2, the xor-sum, then N0..N3 with N_j across V_j
+                // (vertices in ascending id, so the fields are those of Tet20)
+                for (int r = 0; r < 3; ++r) M.rec[8 * tn + r] = v[r];
+                M.rec[8 * tn + 3] = vx;
+                for (int r = 0; r < 4; ++r) M.rec[8 * tn + 4 + r] = int32_t(field[r]);
             } else {
                 M.rec[5 * tn] = vx;
                 for (int r = 0; r < 4; ++r) M.rec[5 * tn + 1 + r] = int32_t(field[r]);

@@ -21,7 +21,9 @@ struct PackedMesh {
                                          //   the neighbour fields N0..N3 by ascending vertex id;
                                          // Tet16 [nt*4]: xor, then NX_j = N_j ^ N_3 for j < 3;
                                          // Tet32N [nt*8]: N0..N3, then each neighbour's xor
-                                         //   (0 where the field is not a tet)
+                                         //   (0 where the field is not a tet);
+                                         // Tet32 [nt*8]: V0, V1, V2 (ascending internal ids),
+                                         //   the xor, then N0..N3 (N_j across V_j)
     std::vector<int32_t> n3;             // Tet16 only [nt]: N_3 (cold, to start walks)
     std::vector<int32_t> tetv;           // [nt*4]   internal vertex ids, ascending (cold)
     std::vector<int32_t> cfv;            // [ntri*4] internal ids of the triangle's vertices in
@@ -33,6 +35,7 @@ struct PackedMesh {
     std::vector<int32_t> t_old2new;      // [nt]
     std::vector<int32_t> tri_verts_user; // [ntri*3] caller vertex ids, ascending
     std::vector<int32_t> seed;           // [G^3]    internal start tet per seed-grid cell
+    int64_t n_regions = 0;               // TM_SFC_HILBERT_REGIONS: regions found
     int32_t G = 1;
     float lo[3] = {0, 0, 0};
     float inv_cell[3] = {0, 0, 0};

@@ -46,6 +46,10 @@
 //          loaded together: one round trip per step, for twice the bytes and
 //          one more L1 lookup per lane than Tet16.  Not one of the paper's
 //          layouts: the paper's xor idea moved one step ahead.
+//   Tet32  32 bytes {V0, V1, V2, VX, N0..N3} (Fig. 2), two 16-byte loads; the
+//          next tet is the neighbour field beside the stored vertex id that
+//          equals the exit vertex, N3 when none does (Algorithms 2-3): no rank,
+//          three compares.
 // Records and points are read by id through structured buffer descriptors: an
 // index past the array reads zero instead of faulting.  The step is
 // branch-free: the loop test is its only branch.
@@ -87,9 +91,10 @@ constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 constexpr int kTet20 = 0;
 constexpr int kTet16 = 1;
 constexpr int kTet32N = 2;
+constexpr int kTet32 = 3;
 
 template <int LAYOUT>
-constexpr uint32_t rec_bytes() { return LAYOUT == kTet20 ? 20u : (LAYOUT == kTet16 ? 16u : 32u); }
+constexpr uint32_t rec_bytes() { return LAYOUT == kTet20 ? 20u : (LAYOUT == kTet16 ? 16u : 32u); }  // Tet32, Tet32N: 32
 
 // gfx9-family buffer descriptor for `count` elements of `stride` bytes.  An
 // access to an index at or past `count` reads zeros (the bound is given in
@@ -119,7 +124,8 @@ __device__ __forceinline__ void keep(uint32_t& v) { asm volatile("" : "+v"(v)); 
 
 // A record as loaded: the xor field and four more words (Tet20: N0..N3 by
 // ascending vertex id; Tet16: NX0..NX2 and 0; Tet32N: N0..N3 and the
-// neighbours' xor-sums w0..w3, no xor field of its own).
+// neighbours' xor-sums w0..w3, no xor field of its own; Tet32: N0..N3 and the
+// stored vertex ids V0..V2 in w0..w2).
 struct Rec {
     int32_t vx;
     uint32_t n0, n1, n2, n3;
@@ -136,6 +142,10 @@ __device__ __forceinline__ Rec load_rec(const Mem& M, uint32_t tet) {
     } else if (LAYOUT == kTet16) {
         const u32x4 a = sbuf_load_b128(M.rec, tet, 0u, 0u, 0);
         return Rec{int32_t(a[0]), a[1], a[2], a[3], 0u, 0u, 0u, 0u, 0u};
+    } else if (LAYOUT == kTet32) {
+        const u32x4 a = sbuf_load_b128(M.rec, tet, 0u, 0u, 0);    // V0, V1, V2, VX
+        const u32x4 b = sbuf_load_b128(M.rec, tet, 16u, 0u, 0);   // N0..N3
+        return Rec{int32_t(a[3]), b[0], b[1], b[2], b[3], a[0], a[1], a[2], 0u};
     } else {
         const u32x4 a = sbuf_load_b128(M.rec, tet, 0u, 0u, 0);
         const u32x4 b = sbuf_load_b128(M.rec, tet, 16u, 0u, 0);
@@ -430,12 +440,22 @@ __device__ __forceinline__ void walk_step_rec(const Mem& M, const Frame& f, cons
     }
     const bool s1 = lane(S1), s2 = lane(S2), s0 = lane(~(S1 | S2));
     const int32_t x = s1 ? w.a1 : (s2 ? w.a2 : w.a0);
-    // rank of the exit vertex x among the tet's four ids (Algorithms 4-5), as its
-    // two bits: the count of ids below x is odd (lo) / at least 2 (hi)
-    const uint64_t b0 = lanes(w.a0 < x), b1 = lanes(w.a1 < x), b2 = lanes(w.a2 < x), b3 = lanes(id3 < x);
-    const bool rlo = lane(b0 ^ b1 ^ b2 ^ b3);
-    const bool rhi = lane(((b0 | b1) & (b2 | b3)) | (b0 & b1) | (b2 & b3));
-    if (LAYOUT == kTet16) {
+    bool rlo = false, rhi = false;
+    if (LAYOUT != kTet32) {
+        // rank of the exit vertex x among the tet's four ids (Algorithms 4-5), as its
+        // two bits: the count of ids below x is odd (lo) / at least 2 (hi)
+        const uint64_t b0 = lanes(w.a0 < x), b1 = lanes(w.a1 < x), b2 = lanes(w.a2 < x), b3 = lanes(id3 < x);
+        rlo = lane(b0 ^ b1 ^ b2 ^ b3);
+        rhi = lane(((b0 | b1) & (b2 | b3)) | (b0 & b1) | (b2 & b3));
+    }
+    if (LAYOUT == kTet32) {
+        // Algorithm 3: the neighbour field beside the stored id equal to x, else N3
+        const bool e0 = lane(lanes(x == int32_t(R.w0)));
+        const bool e1 = lane(lanes(x == int32_t(R.w1)));
+        const bool e2 = lane(lanes(x == int32_t(R.w2)));
+        w.next = e0 ? R.n0 : (e1 ? R.n1 : (e2 ? R.n2 : R.n3));
+        w.cur = int32_t(tet);
+    } else if (LAYOUT == kTet16) {
         // Algorithms 6-7: next = prev ^ NX[rank of id3] ^ NX[rank of x], NX3 = 0
         const uint64_t c0 = lanes(w.a0 < id3), c1 = lanes(w.a1 < id3), c2 = lanes(w.a2 < id3);
         const bool alo = lane(c0 ^ c1 ^ c2);
@@ -1087,6 +1107,9 @@ hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, 
     } else if (m.layout == kTet32N) {
         if (r.tmax) launch_trace_t<true, kTet32N>(m, r, c, s);
         else launch_trace_t<false, kTet32N>(m, r, c, s);
+    } else if (m.layout == kTet32) {
+        if (r.tmax) launch_trace_t<true, kTet32>(m, r, c, s);
+        else launch_trace_t<false, kTet32>(m, r, c, s);
     } else {
         if (r.tmax) launch_trace_t<true, kTet20>(m, r, c, s);
         else launch_trace_t<false, kTet20>(m, r, c, s);
@@ -1110,6 +1133,7 @@ hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_b
     const dim3 g{unsigned(total_blocks)}, b{unsigned(block)};
     if (layout == kTet16) launch_trace_batch_t<kTet16>(d_jobs, n_jobs, g, b, X, steps, s);
     else if (layout == kTet32N) launch_trace_batch_t<kTet32N>(d_jobs, n_jobs, g, b, X, steps, s);
+    else if (layout == kTet32) launch_trace_batch_t<kTet32>(d_jobs, n_jobs, g, b, X, steps, s);
     else launch_trace_batch_t<kTet20>(d_jobs, n_jobs, g, b, X, steps, s);
     return hipGetLastError();
 }
@@ -1123,6 +1147,8 @@ hipError_t launch_locate(const DevMesh& m, int64_t n, const float* pts, int32_t*
         hipLaunchKernelGGL(k_locate<kTet16>, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
     else if (m.layout == kTet32N)
         hipLaunchKernelGGL(k_locate<kTet32N>, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
+    else if (m.layout == kTet32)
+        hipLaunchKernelGGL(k_locate<kTet32>, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
     else
         hipLaunchKernelGGL(k_locate<kTet20>, dim3(unsigned(grid)), dim3(block), 0, s, m, n, pts, out, max_steps);
     return hipGetLastError();

@@ -33,14 +33,40 @@ int main(int argc, char** argv) {
         !read_all(f, nbrs, size_t(4 * nt)) || !read_all(f, cflag, size_t(4 * nt)))
         return 2;
     fclose(f);
-    for (int layout = 0; layout < 3; ++layout) {
-        for (int sfc = 0; sfc < 3; ++sfc) {
-            tm_upload_opts o{layout, sfc, 1, 0};
+    // regions by a plain flood fill (independent of the packer's union-find):
+    // tets joined across faces that are neither constrained nor the boundary
+    std::vector<int32_t> label(size_t(nt), -1);
+    int64_t n_regions = 0;
+    for (int64_t s = 0; s < nt; ++s) {
+        if (label[size_t(s)] >= 0) continue;
+        std::vector<int64_t> stack{s};
+        label[size_t(s)] = int32_t(n_regions);
+        while (!stack.empty()) {
+            const int64_t t = stack.back();
+            stack.pop_back();
+            for (int j = 0; j < 4; ++j) {
+                const int32_t nb = nbrs[size_t(4 * t + j)];
+                if (nb < 0 || cflag[size_t(4 * t + j)] || label[size_t(nb)] >= 0) continue;
+                label[size_t(nb)] = int32_t(n_regions);
+                stack.push_back(nb);
+            }
+        }
+        ++n_regions;
+    }
+    for (int layout = 0; layout < 4; ++layout) {
+        for (int sfc = 0; sfc < 4; ++sfc) {
+            tm_upload_opts o{layout, sfc, 1, 0, 0};
             tetrt::PackedMesh m;
             std::string err;
             const int rc = tetrt::pack_mesh(P.data(), np, tets.data(), nbrs.data(), cflag.data(), nt, o, &m, &err);
-            printf("pack layout %d sfc %d rc %d ntri %lld G %d rec %zu\n", layout, sfc, rc, (long long)m.ntri,
-                   m.G, m.rec.size());
+            // in region order every region's tets are one contiguous run
+            int64_t runs = 0;
+            for (int64_t i = 0; i < nt && rc == 0; ++i)
+                if (i == 0 || label[size_t(m.t_new2old[size_t(i)])] != label[size_t(m.t_new2old[size_t(i - 1)])])
+                    ++runs;
+            printf("pack layout %d sfc %d rc %d ntri %lld G %d rec %zu regions %lld flood %lld runs %lld\n",
+                   layout, sfc, rc, (long long)m.ntri, m.G, m.rec.size(), (long long)m.n_regions,
+                   (long long)n_regions, (long long)runs);
         }
     }
     // corrupted copies: each must be rejected by validation
@@ -61,7 +87,7 @@ int main(int argc, char** argv) {
             while (j < 4 && n2[4 * t + j] < 0) ++j;
             if (j < 4) c2[4 * t + j] = uint8_t(!c2[4 * t + j]);
         }
-        tm_upload_opts o{1, 0, 1, 0};
+        tm_upload_opts o{1, 0, 1, 0, 0};
         tetrt::PackedMesh m;
         std::string err;
         const int rc = tetrt::pack_mesh(P.data(), np, t2.data(), n2.data(), c2.data(), nt, o, &m, &err);

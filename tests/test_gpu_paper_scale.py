@@ -1,6 +1,7 @@
 """Parity at full size: the 12.6M-tet scene with the 1920x1080 camera, traced in
 the launch configuration the benchmark times (Hilbert order, 8x8 pixel tiles,
-256-thread blocks).  The oracle checks a seeded sample of rays one by one;
+the library's automatic block size: 128 threads for camera rays, 256 for binned
+AO rays).  The oracle checks a seeded sample of rays one by one;
 properties that hold for any ray are checked on all of them."""
 import numpy as np
 import pytest
@@ -22,14 +23,15 @@ def scene():
     return m, om, o, d
 
 
-# Tet16 is the benchmark's layout; Tet20 is the paper's GPU layout; Tet32N the one-round-trip variant
-@pytest.fixture(scope="module", params=["tet16", "tet20", "tet32n"])
+# Tet16 is the benchmark's layout; Tet20 is the paper's GPU layout; Tet32 the paper's
+# 32-byte layout; Tet32N the one-round-trip variant
+@pytest.fixture(scope="module", params=["tet16", "tet20", "tet32", "tet32n"])
 def paper(request, scene):
     import paper_2103_02309_amd as tetrt
     m, om, o, d = scene
     mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=request.param)
     res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), want_tets=True,
-                     want_steps=True, block=256)
+                     want_steps=True)
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy() for k, v in res.items()}
     yield m, mesh, om, o, d, got
@@ -68,7 +70,7 @@ def test_primary_benchmark_kernel_identical(paper):
     kernel of its own): on all 2,073,600 rays it gives bit for bit the results
     of the counting kernel that the oracle comparisons below check."""
     m, mesh, om, o, d, got = paper
-    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), block=256)
+    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda())
     torch.cuda.synchronize()
     for k, v in res.items():
         assert np.array_equal(v.cpu().numpy(), got[k], equal_nan=True), k
@@ -80,7 +82,7 @@ def test_primary_benchmark_kernel_identical(paper):
     tetrt.tetmesh_locate(mesh.handle, cam, cam_tet)
     start = cam_tet.expand(o.shape[0]).contiguous()
     assert int(cam_tet.item()) == int(om.locate(o[:1])[0])
-    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), start_tet=start, block=256)
+    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), start_tet=start)
     torch.cuda.synchronize()
     for k, v in res.items():
         assert np.array_equal(v.cpu().numpy(), got[k], equal_nan=True), k
@@ -98,7 +100,7 @@ def test_primary_sampled_vs_oracle(paper):
     assert np.array_equal(sub["hit_tets"][same & (ref["tri"] >= 0)], ref["tets"][same & (ref["tri"] >= 0)])
     assert (sub["steps"] == ref["steps"]).mean() > 0.99
     # the precision variant on the same rays meets the same bar
-    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), block=256, eps=1e-6)
+    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), eps=1e-6)
     torch.cuda.synchronize()
     sub = {k: v.cpu().numpy()[idx] for k, v in res.items()}
     rep = compare(m.points, om.tri_verts, o[idx], d[idx], ref, sub)

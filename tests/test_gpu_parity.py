@@ -29,7 +29,7 @@ def tetrt():
     return tetrt
 
 
-LAYOUTS = ["tet20", "tet16", "tet32n"]
+LAYOUTS = ["tet20", "tet16", "tet32n", "tet32"]
 
 
 @pytest.fixture(scope="module", params=LAYOUTS)
@@ -182,13 +182,18 @@ def test_invalid_inputs(tiny, tetrt):
 
 
 def test_sfc_orders_agree(tetrt, tiny_mesh, tiny_oracle):
+    """Memory order changes no result.  Region order (Sec. "Reordering tetrahedral
+    mesh data"): the small scene has two regions, inside and outside its sphere."""
     m = tiny_mesh
     o, d = random_interior_rays(20000, 23)
     outs = {}
-    for sfc in ("hilbert", "morton", "none"):
+    for sfc in ("hilbert", "morton", "none", "hilbert_regions"):
         mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, sfc=sfc)
+        assert mesh.info["n_regions"] == (2 if sfc == "hilbert_regions" else 0)
         outs[sfc] = _host(mesh.trace(_dev(o), _dev(d)))
         mesh.free()
+    assert all(np.array_equal(outs["hilbert_regions"][k], outs["hilbert"][k], equal_nan=True)
+               for k in outs["hilbert"])
     for sfc in ("morton", "none"):
         same = outs[sfc]["tri"] == outs["hilbert"]["tri"]
         assert same.mean() > 0.9999
@@ -251,7 +256,7 @@ def test_layouts_agree(tetrt, tiny_mesh):
             assert np.array_equal(outs[0][k], other[k], equal_nan=True), k
 
 
-@pytest.mark.parametrize("layout,rec_bytes", [("tet20", 20), ("tet16", 16), ("tet32n", 32)])
+@pytest.mark.parametrize("layout,rec_bytes", [("tet20", 20), ("tet16", 16), ("tet32n", 32), ("tet32", 32)])
 def test_hot_bytes_per_layout(tetrt, tiny_mesh, layout, rec_bytes):
     """The arrays a step reads: one record per tet and one unpadded 12-byte point
     per vertex."""
@@ -367,3 +372,52 @@ def test_concurrent_streams_on_one_handle(tiny, tetrt):
             assert np.array_equal(got1[k], ref1[k], equal_nan=True), k
         for k in ref2:
             assert np.array_equal(got2[k], ref2[k], equal_nan=True), k
+
+
+def _raw_trace(tetrt, handle, O, D, T, out, stream=None, **opts):
+    """trace_closest through the C-ABI without the Mesh wrapper's workspace."""
+    tetrt.binding.trace_closest(handle, O, D, out["tri"], out["t"], out["bary"], tmax=T,
+                                steps=out.get("steps"), stream=stream, **opts)
+
+
+def test_handle_workspace_and_no_workspace(tiny_mesh, tetrt):
+    """Binning without a caller workspace: through the handle's own (sized at
+    upload) the results are those of an unbinned trace, also for traces on two
+    streams one after the other without a synchronisation between them; a handle
+    without one refuses an explicit sort = 2 and traces an automatic one unbinned."""
+    m = tiny_mesh
+    n = 300000                                    # above the automatic binning threshold
+    o, d = random_interior_rays(n, 71)
+    tm = np.random.default_rng(10).uniform(0.05, 0.5, n).astype(np.float32)
+    O, D, T = _dev(o), _dev(d), _dev(tm)
+    plain = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout="tet16")
+    ws_mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout="tet16", bin_rays=n)
+    ref = _host(plain.trace(O, D, tmax=T, want_steps=True, sort=1))
+    # automatic binning with no workspace anywhere: unbinned, same results
+    out = tetrt.outputs(n, "cuda:0", want_steps=True)
+    _raw_trace(tetrt, plain.handle, O, D, T, out)
+    got = _host(out)
+    for k in ref:
+        assert np.array_equal(got[k], ref[k], equal_nan=True), k
+    with pytest.raises(tetrt.TetRTError, match="workspace"):
+        _raw_trace(tetrt, plain.handle, O, D, T, out, sort=2)
+    # the handle's workspace, on two streams back to back
+    outs = [tetrt.outputs(n, "cuda:0", want_steps=True) for _ in range(2)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(2):
+        _raw_trace(tetrt, ws_mesh.handle, O, D, T, outs[0], stream=s1, sort=2)
+        _raw_trace(tetrt, ws_mesh.handle, O, D, T, outs[1], stream=s2, sort=2, sort_chunk_log2=10)
+        torch.cuda.synchronize()
+        for o_ in outs:
+            got = _host(o_)
+            for k in ref:
+                assert np.array_equal(got[k], ref[k], equal_nan=True), k
+    # more rays than the handle's workspace holds: refused when asked for
+    with pytest.raises(tetrt.TetRTError, match="workspace"):
+        big = n + 256                             # past the workspace's rounding
+        O2, D2 = _dev(np.resize(o, (big, 3))), _dev(np.resize(d, (big, 3)))
+        _raw_trace(tetrt, ws_mesh.handle, O2, D2, _dev(np.resize(tm, big)),
+                   tetrt.outputs(big, "cuda:0"), sort=2)
+    plain.free()
+    ws_mesh.free()

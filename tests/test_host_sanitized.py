@@ -51,9 +51,20 @@ def test_pack_under_sanitizers(driver, tmp_path):
     lines = res.stdout.splitlines()
     assert lines[-1] == "done"
     packs = [l for l in lines if l.startswith("pack ")]
-    assert len(packs) == 9 and all(" rc 0 " in l for l in packs), packs
+    assert len(packs) == 16 and all(" rc 0 " in l for l in packs), packs
     # the constrained-face count does not depend on layout or curve
     assert len({l.split(" ntri ")[1].split()[0] for l in packs}) == 1
+    # region order (sfc 3): as many regions as the flood fill finds (inside the
+    # spheres and outside: more than one), each stored as one contiguous run
+    for l in packs:
+        f = l.split()
+        regions, flood, runs = int(f[f.index("regions") + 1]), int(f[f.index("flood") + 1]), int(
+            f[f.index("runs") + 1])
+        assert flood >= 2
+        if " sfc 3 " in l:
+            assert regions == flood == runs, l
+        else:
+            assert regions == 0 and runs > flood, l
     bad = [l for l in lines if l.startswith("bad ")]
     assert len(bad) == 5 and all(" rc -2:" in l for l in bad), bad
 
