@@ -94,8 +94,9 @@ typedef struct {
     int32_t sfc;       /* TM_SFC_* */
     int32_t validate;  /* 1 = check the mesh before packing (recommended) */
     int32_t seed_grid; /* cells per axis of the point-location seed grid; 0 = automatic */
-    int64_t bin_rays;  /* rays the handle's own binning workspace holds (4 bytes each),
-                          allocated here, once; 0 = none.  trace_closest bins through it
+    int64_t bin_rays;  /* rays the handle's own workspace serves (8 bytes each and about
+                          9 KB), allocated here, once; 0 = none.  trace_closest uses it for
+                          binning, the queue kernel and the precision variant's two passes
                           when the caller passes no workspace of its own.  0 <= bin_rays
                           < 2^31 */
 } tm_upload_opts;
@@ -119,8 +120,12 @@ typedef struct {
     int32_t block;       /* threads per block: 64, 128 or 256 (0 = automatic: 256 when the
                             rays are binned or in a caller's order, else 128) */
     int32_t kernel;      /* 0 = automatic, 1 = one lane per ray, 2 = persistent lanes that
-                            take further rays as theirs finish */
-    int32_t refill;      /* persistent lanes: finished lanes per wavefront that trigger a
+                            take further rays as theirs finish, 3 = persistent waves that
+                            drain a work queue: each wave takes chunks of queue_chunk rays
+                            from a global counter per XCD (its own die's range first, then
+                            the others'), stages their ids in LDS and refills its finished
+                            lanes from them (needs a workspace, as binning does) */
+    int32_t refill;      /* kernels 2 and 3: finished lanes per wavefront that trigger a
                             refill, 1..64 (0 = 16) */
     int32_t grid_cap;    /* persistent lanes: at most this many blocks (0 = enough blocks
                             to fill every compute unit) */
@@ -148,11 +153,12 @@ typedef struct {
                             and determinants in float64 from the float32 points, basis and
                             origin; the start tet's exit face is then also found in float64.
                             With the scene extent 1, eps >= 1e-6 covers float32 rounding */
-    void* workspace;     /* device scratch for binning (tetmesh_trace_workspace gives the
-                            need), or NULL: the handle's own workspace (tm_upload_opts.bin_rays)
-                            is then used when it is large enough.  A binned trace with
-                            neither: sort = 2 fails (TM_ERR_ARG), sort = 0 traces the rays
-                            unbinned (the same results) */
+    void* workspace;     /* device scratch for binning and for kernel 3's queue
+                            (tetmesh_trace_workspace gives the need), or NULL: the handle's own
+                            workspace (tm_upload_opts.bin_rays) is then used when it is large
+                            enough.  A binned trace with neither: sort = 2 or kernel = 3 fails
+                            (TM_ERR_ARG), sort = 0 traces the rays unbinned (the same
+                            results) */
     int64_t workspace_bytes; /* size of workspace */
     int32_t* fp64_steps; /* device int32 [n_rays] or NULL: out: walk steps decided in float64
                             (0 when eps = 0) */
@@ -160,6 +166,9 @@ typedef struct {
                             takes ray order[j]; a permutation of 0..n_rays-1, e.g. from
                             tetmesh_bin_rays; entries out of range are skipped).  Replaces
                             the call's own binning (sort is then ignored) */
+    int32_t queue_chunk; /* kernel 3: rays a wave takes from the queue at a time, a multiple
+                            of 64 in [64, 4096] (0 = 256) */
+    int32_t reserved;
 } tm_trace_opts;
 
 /*
@@ -305,10 +314,12 @@ typedef struct tm_batch_s* tm_batch;
 int tm_batch_create(int32_t max_jobs, int64_t max_rays, tm_batch* out);
 
 /* tm_batch_set -- replace the batch's jobs.  jobs host [n_jobs] (0 <= n_jobs <=
- * max_jobs), copied.  opts as for trace_closest, except: kernel 0 or 1, eps = 0,
- * xcd_blocks, refill, grid_cap, workspace, fp64_steps and order are ignored,
- * xcds = 0 means round-robin placement (xcds > 1: one contiguous range of the
- * whole launch per XCD), and the binning chunk size is one for all jobs
+ * max_jobs), copied.  opts as for trace_closest, except: kernel 0, 1 or 3 (3:
+ * persistent waves drain one queue of every job's rays, queue_chunk and refill
+ * as for trace_closest; xcds = its number of per-XCD ranges, 0 = the device's
+ * XCDs), eps = 0, xcd_blocks, grid_cap, workspace, fp64_steps and order are
+ * ignored, with kernel 1 xcds = 0 means round-robin placement (xcds > 1: one
+ * contiguous range of the whole launch per XCD), and the binning chunk size is one for all jobs
  * (sort = 0 bins the jobs that carry tmax and have at least 2^18 rays).  The new table is copied to the device on
  * hip_stream, after the batch's previous table copy has left the staging
  * buffer; launches on that stream that follow see it.  A launch of the batch on
@@ -318,8 +329,9 @@ int tm_batch_set(tm_batch b, int32_t n_jobs, const tm_job* jobs, const tm_trace_
                  void* hip_stream);
 
 /* tm_batch_launch -- enqueue the walk of every ray of every job on hip_stream:
- * at most two kernel launches (binning, walk), with no allocation, memory set,
- * copy or synchronisation, so a caller may capture it into a HIP graph.
+ * at most three kernel launches (binning, the queue's counter reset with kernel
+ * 3, walk), with no allocation, memory set, copy or synchronisation, so a
+ * caller may capture it into a HIP graph.
  * Errors: TM_ERR_ARG, TM_ERR_HIP. */
 int tm_batch_launch(tm_batch b, void* hip_stream);
 
@@ -333,8 +345,10 @@ int tm_batch_graph_launch(tm_batch b, void* hip_stream);
 /* tm_batch_tune -- autotuner: times tm_batch_launch on the current jobs for
  * each block size (64, 128, 256), binning setting (off; on with 2^11, 2^12,
  * 2^13 rays per chunk) and die placement (round-robin; one contiguous range of
- * blocks per XCD), reps timed launches each after one warm-up, with HIP events
- * on hip_stream, and keeps the fastest.  Overwrites the jobs' outputs
+ * blocks per XCD) of the one-lane-per-ray kernel, and for the queue kernel
+ * each binning setting, rays per wave fetch (queue_chunk 64, 256, 1024) and
+ * refill threshold (8, 32), reps timed launches each after one warm-up, with
+ * HIP events on hip_stream, and keeps the fastest.  Overwrites the jobs' outputs
  * (with the same results).  Synchronous.  chosen host, nullable: receives the
  * options kept; ms host, nullable: their mean launch time in milliseconds.
  * Errors: TM_ERR_ARG, TM_ERR_HIP. */

@@ -83,9 +83,12 @@ def ray_triangle_gap(points, tri_verts, tri, orig, dirs):
 
 
 def compare(points, tri_verts, orig, dirs, ref, got, tmax=None, extent=1.0, edge_tol=1e-6,
-            t_rtol=1e-5, bary_tol=1e-4, tmax_rtol=1e-6, min_identical=0.9999):
+            t_rtol=1e-5, bary_tol=1e-4, tmax_rtol=1e-6, min_identical=0.9999, t_atol=0.0):
     """Compare ``got`` (numpy dict: tri, t, bary) with oracle results ``ref``.
-    Returns a report dict with ``ok`` and the details."""
+    Returns a report dict with ``ok`` and the details.  ``t_atol`` (scalar or per
+    ray, default 0): an absolute allowance added to ``t_rtol * |t|`` on matched
+    hits, for rays that are compared with the oracle's on slightly different
+    inputs (secondary rays rebuilt from hits of other precision)."""
     P = np.asarray(points, dtype=np.float64)
     o = np.asarray(orig, dtype=np.float64).reshape(-1, 3)
     d = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
@@ -150,9 +153,10 @@ def compare(points, tri_verts, orig, dirs, ref, got, tmax=None, extent=1.0, edge
     rep["unexplained"] = mism[~explained].tolist()[:50]
     rep["n_unexplained"] = int((~explained).sum())
     hit = same & (rt >= 0)
+    atol = np.broadcast_to(np.asarray(t_atol, np.float64), (n,))[hit]
     with np.errstate(invalid="ignore", divide="ignore"):
-        rel = np.abs(np.asarray(got["t"], np.float64)[hit] - np.asarray(ref["t"])[hit]) / np.abs(
-            np.asarray(ref["t"])[hit])
+        rel = np.maximum(np.abs(np.asarray(got["t"], np.float64)[hit] - np.asarray(ref["t"])[hit]) - atol,
+                         0.0) / np.abs(np.asarray(ref["t"])[hit])
         db = np.abs(np.asarray(got["bary"], np.float64)[hit] - np.asarray(ref["bary"])[hit])
     rep["max_t_rel"] = float(np.nanmax(rel)) if rel.size else 0.0
     rep["max_bary"] = float(np.nanmax(db)) if db.size else 0.0

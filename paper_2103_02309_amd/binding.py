@@ -34,10 +34,11 @@ class _TraceOpts(C.Structure):
                 ("refill", C.c_int32), ("grid_cap", C.c_int32), ("xcds", C.c_int32),
                 ("sort", C.c_int32), ("sort_chunk_log2", C.c_int32), ("sort_cells_log2", C.c_int32),
                 ("sort_dirq", C.c_int32), ("xcd_blocks", C.c_int32), ("eps", C.c_float), ("workspace", C.c_void_p), ("workspace_bytes", C.c_int64),
-                ("fp64_steps", C.c_void_p), ("order", C.c_void_p)]
+                ("fp64_steps", C.c_void_p), ("order", C.c_void_p), ("queue_chunk", C.c_int32),
+                ("reserved", C.c_int32)]
 
 _TRACE_KEYS = ("max_steps", "block", "kernel", "refill", "grid_cap", "xcds", "sort",
-               "sort_chunk_log2", "sort_cells_log2", "sort_dirq", "xcd_blocks")
+               "sort_chunk_log2", "sort_cells_log2", "sort_dirq", "xcd_blocks", "queue_chunk")
 
 
 def _trace_opts(kw, workspace=None, fp64_steps=None, n=0):
@@ -242,7 +243,7 @@ def trace_closest(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, s
 
 
 def tetmesh_trace_workspace(handle, n_rays, has_tmax, **opts):
-    o = _trace_opts(dict(opts))
+    o = _trace_opts(dict(opts), n=int(n_rays))
     b = C.c_int64()
     _check(_load().tetmesh_trace_workspace(C.c_void_p(handle), int(n_rays),
                                            C.c_void_p(1 if has_tmax else 0), C.byref(o),
@@ -337,7 +338,8 @@ def tm_batch_tune(batch, reps=5, stream=None):
     ms = C.c_float()
     _check(_load().tm_batch_tune(C.c_void_p(batch), int(reps), _stream(stream), C.byref(o),
                                  C.byref(ms)))
-    return {k: getattr(o, k) for k in ("block", "sort", "sort_chunk_log2", "xcds")}, ms.value
+    return {k: getattr(o, k) for k in ("block", "sort", "sort_chunk_log2", "xcds", "kernel", "queue_chunk",
+                                       "refill")}, ms.value
 
 
 def tm_batch_free(batch):
@@ -470,8 +472,8 @@ class Mesh:
         """Trace into caller tensors.  A trace that bins its rays (``sort``) without a
         ``workspace`` gets one from torch's allocator here, held on the stream it runs
         on, so the library itself never allocates."""
-        if workspace is None and opts.get("order") is None:
-            wo = {k: v for k, v in opts.items() if k in _TRACE_KEYS}
+        if workspace is None:
+            wo = {k: v for k, v in opts.items() if k in _TRACE_KEYS or k in ("eps", "order")}
             need = self.workspace_bytes(int(orig.shape[0]), tmax is not None, **wo)
             if need > 0:
                 workspace = torch.empty(need, dtype=torch.uint8, device=orig.device)

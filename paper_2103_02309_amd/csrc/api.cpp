@@ -130,7 +130,9 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
     if (o.max_steps < 0) return fail(TM_ERR_ARG, "%s: negative max_steps", name);
     if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
         return fail(TM_ERR_ARG, "%s: block must be 64, 128 or 256", name);
-    if (o.kernel < 0 || o.kernel > 2) return fail(TM_ERR_ARG, "%s: kernel must be 0, 1 or 2", name);
+    if (o.kernel < 0 || o.kernel > 3) return fail(TM_ERR_ARG, "%s: kernel must be 0, 1, 2 or 3", name);
+    if (o.queue_chunk < 0 || o.queue_chunk > 4096 || (o.queue_chunk & 63))
+        return fail(TM_ERR_ARG, "%s: queue_chunk must be a multiple of 64 in [64, 4096]", name);
     if (o.refill < 0 || o.refill > 64) return fail(TM_ERR_ARG, "%s: refill must be in [0, 64]", name);
     if (o.grid_cap < 0) return fail(TM_ERR_ARG, "%s: negative grid_cap", name);
     if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "%s: xcds must be in [0, 64]", name);
@@ -138,7 +140,7 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
         return fail(TM_ERR_ARG, "%s: xcd_blocks must be in [0, 65536]", name);
     if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "%s: sort must be 0, 1 or 2", name);
     if (!(o.eps >= 0.0f) || !(o.eps < 1.0f)) return fail(TM_ERR_ARG, "%s: eps must be in [0, 1)", name);
-    if (o.eps > 0.0f && o.kernel == 2)
+    if (o.eps > 0.0f && o.kernel >= 2)
         return fail(TM_ERR_ARG, "%s: the precision variant (eps > 0) runs one lane per ray", name);
     if (o.workspace_bytes < 0 || (o.workspace_bytes > 0 && !o.workspace))
         return fail(TM_ERR_ARG, "%s: bad workspace", name);
@@ -149,17 +151,30 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
     int rc = sort_config(m, o, n_rays, d_tmax != nullptr, &sc, &binned);
     if (rc != TM_OK) return rc;
     if (o.order) binned = false;   // the caller's order replaces the call's binning
-    const int64_t need = binned ? sort_workspace_bytes(n_rays) : 0;
-    // where the binning permutation goes: the given fixed workspace, the caller's,
-    // or the handle's own; with none of them large enough an explicit sort = 2
-    // is an error and the automatic choice traces the rays unbinned
+    const bool queue = o.kernel == 3;
+    // workspace: the binning permutation, then (kernel 3) the queue's counters and
+    // its one-entry job table
+    int64_t perm_bytes = binned ? sort_workspace_bytes(n_rays) : 0;
+    const int64_t queue_bytes = queue ? queue_workspace_bytes() : 0;
+    // the precision variant's two-pass form: a counter and a list of deferred rays
+    // (without room for them it runs in one pass, with the same results)
+    int64_t defer_bytes = (o.eps > 0.0f && o.kernel != 2) ? 256 + sort_workspace_bytes(n_rays) : 0;
+    // where it goes: the given fixed workspace, the caller's, or the handle's own;
+    // with none of them large enough an explicit sort = 2 or kernel = 3 is an
+    // error and the automatic choice traces the rays unbinned
     void* ws = nullptr;
     bool handle_ws = false;
-    if (binned) {
+    while (perm_bytes + queue_bytes + defer_bytes > 0) {
+        const int64_t need = perm_bytes + queue_bytes + defer_bytes;
+        const int64_t avail = fixed_ws ? fixed_ws_bytes : (o.workspace ? o.workspace_bytes : m->ws_bytes);
+        if (avail < need && defer_bytes > 0) {
+            defer_bytes = 0;
+            continue;
+        }
         if (fixed_ws) {
-            if (fixed_ws_bytes < need)
+            if (perm_bytes > fixed_ws_bytes - kFixedExtraBytes || fixed_ws_bytes < need)
                 return fail(TM_ERR_ARG, "%s: %lld rays to bin, at most %lld", name, (long long)n_rays,
-                            (long long)(fixed_ws_bytes / 4));
+                            (long long)((fixed_ws_bytes - kFixedExtraBytes) / 4));
             ws = fixed_ws;
         } else if (o.workspace) {
             if (o.workspace_bytes < need)
@@ -169,12 +184,16 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
         } else if (m->ws_bytes >= need) {
             ws = m->ws;
             handle_ws = true;
-        } else if (o.sort == 2) {
-            return fail(TM_ERR_ARG, "%s: binning %lld rays needs a workspace of %lld bytes (opts.workspace, "
-                        "or tm_upload_opts.bin_rays >= n_rays)", name, (long long)n_rays, (long long)need);
+        } else if (o.sort == 2 || queue) {
+            return fail(TM_ERR_ARG, "%s: %s needs a workspace of %lld bytes (opts.workspace, or "
+                        "tm_upload_opts.bin_rays >= n_rays)", name, queue ? "the queue kernel" : "binning",
+                        (long long)need);
         } else {
             binned = false;
+            perm_bytes = 0;
+            continue;
         }
+        break;
     }
     RayArgs r;
     r.perm = o.order;
@@ -211,6 +230,22 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
     // measured workload and runs only when asked for)
     c.kernel = o.kernel ? o.kernel : 1;
     c.eps = o.eps;
+    if (queue) {
+        char* base = static_cast<char*>(ws) + perm_bytes;
+        c.queue.cursor = reinterpret_cast<uint32_t*>(base);
+        c.queue.chunk = uint32_t(o.queue_chunk ? o.queue_chunk : 256);
+        c.queue.n_chunks = uint32_t((n_rays + c.queue.chunk - 1) / c.queue.chunk);
+        c.queue.xcds = uint32_t(o.xcds ? o.xcds : xcd_count(m->cus));
+        c.queue.refill = c.refill;
+        c.queue_job = reinterpret_cast<Job*>(base + kQueueCursorBytes);
+    }
+    c.defer_count = nullptr;
+    c.defer_list = nullptr;
+    if (defer_bytes > 0) {
+        char* base = static_cast<char*>(ws) + perm_bytes + queue_bytes;
+        c.defer_count = reinterpret_cast<uint32_t*>(base);
+        c.defer_list = reinterpret_cast<int32_t*>(base + 256);
+    }
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     hipError_t e;
     std::unique_lock<std::mutex> lock(m->ws_mu, std::defer_lock);
@@ -322,7 +357,8 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     }
     if (o.bin_rays > 0) {
         // the handle's binning workspace, allocated once here (traces never allocate)
-        const int64_t need = tetrt::sort_workspace_bytes(o.bin_rays);
+        // room for binning, the queue kernel and the precision variant's two passes
+        const int64_t need = 2 * tetrt::sort_workspace_bytes(o.bin_rays) + 256 + tetrt::queue_workspace_bytes();
         void* p = nullptr;
         hipError_t e = hipMalloc(&p, size_t(need));
         if (e == hipSuccess) {
@@ -413,7 +449,9 @@ int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_prese
     bool binned = false;
     int rc = sort_config(m, o, n_rays, d_tmax_present != nullptr, &sc, &binned);
     if (rc != TM_OK) return rc;
-    *bytes = binned ? tetrt::sort_workspace_bytes(n_rays) : 0;
+    if (o.order) binned = false;
+    *bytes = (binned ? tetrt::sort_workspace_bytes(n_rays) : 0) + (o.kernel == 3 ? tetrt::queue_workspace_bytes() : 0) +
+             ((o.eps > 0.0f && o.kernel != 2) ? 256 + tetrt::sort_workspace_bytes(n_rays) : 0);
     return TM_OK;
 }
 

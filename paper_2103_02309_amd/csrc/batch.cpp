@@ -4,6 +4,7 @@
 // finds its job by a binary search over the table.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -26,9 +27,13 @@ struct Shape {
     int32_t n_jobs = -1, block = 0, chunk_log2 = 0, layout = -1, xcds = 1;
     int64_t blocks = -1, chunks = -1;
     bool steps = false;   // some job asks for step counts
+    int32_t kernel = 1;   // 1 = one lane per ray, 3 = persistent waves on a queue
+    int32_t qchunk = 0, refill = 0;   // kernel 3: rays per wave fetch, refill threshold
+    int64_t qchunks = 0;  // kernel 3: chunks over all jobs
     bool operator==(const Shape& o) const {
         return n_jobs == o.n_jobs && block == o.block && chunk_log2 == o.chunk_log2 && layout == o.layout &&
-               xcds == o.xcds && blocks == o.blocks && chunks == o.chunks && steps == o.steps;
+               xcds == o.xcds && blocks == o.blocks && chunks == o.chunks && steps == o.steps &&
+               kernel == o.kernel && qchunk == o.qchunk && refill == o.refill && qchunks == o.qchunks;
     }
 };
 
@@ -42,6 +47,7 @@ struct tm_batch_s {
     tetrt::Job* d_table = nullptr;
     tetrt::Job* h_stage = nullptr;   // pinned staging copy of the table
     int32_t* d_perm = nullptr;       // binning permutations of every job
+    uint32_t* d_cursor = nullptr;    // the queue kernel's counters
     hipEvent_t staged = nullptr;     // recorded after the last table copy
     bool copy_recorded = false;
     Shape shape;                     // of the current table
@@ -69,6 +75,7 @@ void release(tm_batch_s* b) {
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->d_table) (void)hipFree(b->d_table);
     if (b->d_perm) (void)hipFree(b->d_perm);
+    if (b->d_cursor) (void)hipFree(b->d_cursor);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
 }
 
@@ -81,15 +88,21 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
     if (o.max_steps < 0) return fail(TM_ERR_ARG, "tm_batch_set: negative max_steps");
     if (o.block != 0 && o.block != 64 && o.block != 128 && o.block != 256)
         return fail(TM_ERR_ARG, "tm_batch_set: block must be 64, 128 or 256");
-    if (o.kernel != 0 && o.kernel != 1)
-        return fail(TM_ERR_ARG, "tm_batch_set: batches run one lane per ray (kernel 0 or 1)");
+    if (o.kernel != 0 && o.kernel != 1 && o.kernel != 3)
+        return fail(TM_ERR_ARG, "tm_batch_set: batches run one lane per ray or persistent waves on a queue "
+                                "(kernel 0, 1 or 3)");
+    if (o.queue_chunk < 0 || o.queue_chunk > 4096 || (o.queue_chunk & 63))
+        return fail(TM_ERR_ARG, "tm_batch_set: queue_chunk must be a multiple of 64 in [64, 4096]");
+    if (o.refill < 0 || o.refill > 64) return fail(TM_ERR_ARG, "tm_batch_set: refill must be in [0, 64]");
     if (o.eps != 0.0f) return fail(TM_ERR_ARG, "tm_batch_set: the precision variant (eps > 0) is not batched");
     if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "tm_batch_set: sort must be 0, 1 or 2");
     if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "tm_batch_set: xcds must be in [0, 64]");
     const int32_t block = o.block ? o.block : 256;
     const int32_t chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 12;
     table->assign(size_t(n_jobs), tetrt::Job{});
-    int64_t blocks = 0, chunks = 0, rays = 0, perm_at = 0;
+    const int32_t kernel = o.kernel == 3 ? 3 : 1;
+    const int32_t qchunk = o.queue_chunk ? o.queue_chunk : 256;
+    int64_t blocks = 0, chunks = 0, rays = 0, perm_at = 0, qchunks = 0;
     int32_t layout = -1;
     for (int32_t k = 0; k < n_jobs; ++k) {
         const tm_job& j = jobs[k];
@@ -135,6 +148,8 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
         r.max_steps = o.max_steps > 0 ? o.max_steps : 65536;
         J.block0 = blocks;
         blocks += (j.n_rays + block - 1) / block;
+        J.qchunk0 = qchunks;
+        qchunks += (j.n_rays + qchunk - 1) / qchunk;
         J.chunk0 = chunks;
         if (binned && j.n_rays > 0) {
             r.perm = b->d_perm + perm_at;
@@ -148,10 +163,16 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
     shape->layout = layout < 0 ? 0 : layout;
     shape->blocks = blocks;
     shape->chunks = chunks;
+    shape->kernel = kernel;
+    shape->qchunk = qchunk;
+    shape->refill = o.refill ? o.refill : 16;
+    shape->qchunks = qchunks;
+    if (kernel == 3 && qchunks >= int64_t(0xFFFFFFFFu))
+        return fail(TM_ERR_ARG, "tm_batch_set: too many queue chunks (raise queue_chunk)");
     // automatic: round-robin placement.  One contiguous range per XCD over a
     // whole batch splits jobs of unequal walks unevenly over the XCDs (measured
     // slower on many-mesh batches); the tuner tries it
-    shape->xcds = o.xcds ? o.xcds : 1;
+    shape->xcds = o.xcds ? o.xcds : (kernel == 3 ? tetrt::xcd_count(b->cus) : 1);
     return TM_OK;
 }
 
@@ -186,6 +207,15 @@ hipError_t enqueue(const tm_batch_s* b, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (sh.chunks > 0) e = tetrt::launch_sort_batch(b->d_table, sh.n_jobs, sh.chunks, sh.chunk_log2, s);
     if (e != hipSuccess) return e;
+    if (sh.kernel == 3) {
+        tetrt::Queue q;
+        q.cursor = b->d_cursor;
+        q.n_chunks = uint32_t(sh.qchunks);
+        q.chunk = uint32_t(sh.qchunk);
+        q.xcds = uint32_t(std::max(1, sh.xcds));
+        q.refill = sh.refill;
+        return tetrt::launch_trace_batch_queue(b->d_table, sh.n_jobs, q, sh.layout, sh.steps, b->cus, s);
+    }
     return tetrt::launch_trace_batch(b->d_table, sh.n_jobs, sh.blocks, sh.block, sh.layout, sh.xcds, sh.steps,
                                      s);
 }
@@ -227,6 +257,7 @@ int tm_batch_create(int32_t max_jobs, int64_t max_rays, tm_batch* out) {
     hipError_t e;
     if ((e = hipMalloc(&b->d_table, table_bytes)) != hipSuccess ||
         (e = hipMalloc(&b->d_perm, perm_bytes)) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&b->d_cursor), size_t(tetrt::kQueueCursorBytes))) != hipSuccess ||
         (e = hipHostMalloc(&b->h_stage, table_bytes, hipHostMallocDefault)) != hipSuccess) {
         (void)hipGetLastError();
         release(b);
@@ -312,19 +343,41 @@ int tm_batch_tune(tm_batch b, int32_t reps, void* hip_stream, tm_trace_opts* cho
     }
     static const int32_t kBlocks[3] = {64, 128, 256};
     static const int32_t kChunks[4] = {0, 11, 12, 13};  // 0 = no binning
+    static const int32_t kQChunks[3] = {64, 256, 1024};
+    static const int32_t kRefills[2] = {8, 32};
     const int32_t xcd_opts[2] = {1, tetrt::xcd_count(b->cus)};
-    tm_trace_opts best = base;
-    float best_ms = -1.0f;
-    rc = TM_OK;
-    for (int32_t blk : kBlocks) {
-        for (int32_t cand = 0; cand < 8 && rc == TM_OK; ++cand) {
+    // candidates: the one-lane-per-ray kernel over block size x binning x placement,
+    // then the queue kernel over binning x rays per fetch x refill threshold
+    std::vector<tm_trace_opts> cands;
+    for (int32_t blk : kBlocks)
+        for (int32_t cand = 0; cand < 8; ++cand) {
             const int32_t ch = kChunks[cand % 4];
             tm_trace_opts o = base;
+            o.kernel = 1;
             o.block = blk;
             o.sort = ch ? 2 : 1;
             o.sort_chunk_log2 = ch ? ch : base.sort_chunk_log2;
             o.xcds = xcd_opts[cand / 4];
             if (cand >= 4 && o.xcds == 1) continue;   // a device with one XCD
+            cands.push_back(o);
+        }
+    for (int32_t ch : kChunks)
+        for (int32_t qc : kQChunks)
+            for (int32_t rf : kRefills) {
+                tm_trace_opts o = base;
+                o.kernel = 3;
+                o.sort = ch ? 2 : 1;
+                o.sort_chunk_log2 = ch ? ch : base.sort_chunk_log2;
+                o.queue_chunk = qc;
+                o.refill = rf;
+                o.xcds = 0;
+                cands.push_back(o);
+            }
+    tm_trace_opts best = base;
+    float best_ms = -1.0f;
+    rc = TM_OK;
+    {
+        for (const tm_trace_opts& o : cands) {
             if ((rc = set_jobs(b, n_jobs, jobs.data(), o, s)) != TM_OK) break;
             if ((e = enqueue(b, s)) != hipSuccess || (e = hipEventRecord(e0, s)) != hipSuccess) {
                 rc = hip_fail(e, "tm_batch_tune: launch");
@@ -345,7 +398,6 @@ int tm_batch_tune(tm_batch b, int32_t reps, void* hip_stream, tm_trace_opts* cho
                 best = o;
             }
         }
-        if (rc != TM_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

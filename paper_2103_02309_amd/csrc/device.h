@@ -49,9 +49,23 @@ struct RayArgs {
     int32_t max_steps;
 };
 
+// Work queue of the persistent-wave kernel: the ray order is cut into chunks of
+// `chunk` rays, split into `xcds` contiguous ranges, one per accelerator die;
+// each range has a counter (cursor[32 x], zero when the launch starts) from
+// which the waves of that die take chunks, and a die whose range is exhausted
+// takes chunks from the others' ranges.
+struct Queue {
+    uint32_t* cursor;       // [32 * xcds] counters, one per 128-byte line
+    uint32_t n_chunks;      // chunks over all jobs
+    uint32_t chunk;         // rays per chunk: 64, 128 or 256
+    uint32_t xcds;          // ranges (1 = one shared range)
+    int32_t refill;         // finished lanes of a wave that trigger a refill (1..64)
+};
+constexpr int64_t kQueueCursorBytes = 32 * 4 * 64;   // room for 64 dies
+
 struct LaunchCfg {
     int32_t block;          // threads per block (64, 128 or 256)
-    int32_t kernel;         // 1 = one lane per ray, 2 = persistent lanes
+    int32_t kernel;         // 1 = one lane per ray, 2 = persistent lanes, 3 = persistent waves on a queue
     int32_t refill;         // persistent: finished lanes per wave that trigger a refill
     int32_t waves_per_simd; // persistent: resident waves per SIMD to launch for
     int32_t cus;            // compute units of the device
@@ -59,6 +73,10 @@ struct LaunchCfg {
     int32_t xcds;           // one lane per ray: XCDs the blocks are renumbered for (1 = off)
     int32_t xcd_blocks;     // consecutive blocks per XCD (0 = one contiguous range each)
     float eps;              // > 0: precision variant (one lane per ray)
+    Queue queue;            // kernel 3
+    struct Job* queue_job;  // kernel 3: device room for a one-entry job table
+    uint32_t* defer_count;  // eps > 0, non-null: two passes (counter and list of deferred rays)
+    int32_t* defer_list;    //   list: room for every ray
 };
 
 hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s);
@@ -76,6 +94,9 @@ struct SortCfg {
 };
 
 int64_t sort_workspace_bytes(int64_t n);
+// Workspace of the queue kernel in a single-mesh trace: its counters and a
+// one-entry job table.
+int64_t queue_workspace_bytes();
 
 // One job of a batched launch: a mesh, its rays, and where its blocks and
 // binning chunks start in the launch.  Lives in device memory.
@@ -85,6 +106,7 @@ struct Job {
     SortCfg sc;
     int64_t block0;           // first block of this job in the trace launch
     int64_t chunk0;           // first chunk of this job in the binning launch
+    int64_t qchunk0;          // first chunk of this job in the persistent-wave queue
 };
 
 // One launch over all jobs (table in device memory, block0 ascending); jobs
@@ -93,6 +115,10 @@ struct Job {
 // some job has a step-count array (the kernel then keeps per-ray counts).
 hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_blocks, int32_t block,
                               int32_t layout, int32_t xcds, bool steps, hipStream_t s);
+// The same walk by persistent waves draining the queue q over every job's rays
+// (zeroes q's counters first, with a kernel of its own); `cus` sizes the grid.
+hipError_t launch_trace_batch_queue(const Job* d_jobs, int32_t n_jobs, const Queue& q, int32_t layout,
+                                    bool steps, int32_t cus, hipStream_t s);
 // Binning of every job's rays (chunks of 2^chunk_log2; perm pointers in the table).
 hipError_t launch_sort_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_chunks,
                              int32_t chunk_log2, hipStream_t s);

@@ -47,6 +47,10 @@ inline int32_t xcd_count(int cus) { return cus >= 64 ? cus / 32 : 1; }
 int sort_config(const tm_mesh_s* m, const tm_trace_opts& o, int64_t n, bool has_tmax, SortCfg* c,
                 bool* on);
 
+// Room beyond the binning permutation in a fixed workspace (the queue kernel's
+// counters and job entry).
+constexpr int64_t kFixedExtraBytes = 32768;
+
 // The body of trace_closest.  fixed_ws (non-null): the binning workspace to
 // use instead of the caller's or the handle's (fixed_ws_bytes long); `name`
 // prefixes error messages.

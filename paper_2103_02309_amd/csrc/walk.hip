@@ -409,9 +409,11 @@ __device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, f
 // step finishes; for a lane whose walk ends there the index is a face flag or
 // the boundary mark, beyond the record count, and the buffer bound makes the
 // load return zeros without touching memory.
+// unsure (given, with PREC false): the step only tests whether its float32
+// decision is unsure -- the test of the precision variant -- and reports it.
 template <bool DEPTH, int LAYOUT, bool PREC, bool LINK = false, bool PIPE = false>
 __device__ __forceinline__ void walk_step_rec(const Mem& M, const Frame& f, const Depth& g, Walk& w,
-                                              Prec& pc, const Rec& R, Rec* ahead) {
+                                              Prec& pc, const Rec& R, Rec* ahead, bool* unsure_out = nullptr) {
     const uint32_t tet = w.next;
     const int32_t id3 = w.a0 ^ w.a1 ^ w.a2 ^ (LAYOUT == kTet32N ? w.vxn : R.vx);
     const float4 P = load_pt(M, uint32_t(id3));
@@ -419,18 +421,33 @@ __device__ __forceinline__ void walk_step_rec(const Mem& M, const Frame& f, cons
     project(f, P, q3x, q3y);
     // Algorithm 1 as lane masks: the exit face drops slot 1 when det(q3,q0) < 0 and
     // det(q3,q2) >= 0, slot 2 when det(q3,q0) >= 0 and det(q3,q1) < 0, else slot 0
-    const uint64_t N0 = lanes(det2_neg(q3x, q3y, w.q0x, w.q0y));
-    const uint64_t N1 = lanes(det2_neg(q3x, q3y, w.q1x, w.q1y));
-    const uint64_t P2 = lanes(det2_nonneg(q3x, q3y, w.q2x, w.q2y));
+    uint64_t N0, N1, P2;
+    bool unsure = false;
+    if (PREC || unsure_out) {
+        // the determinants as values, for the unsure test too; their signs decide as
+        // the comparisons of the rounded products do (a rounded difference of finite
+        // values is negative exactly when the first product is below the second)
+        const float d0 = det2(q3x, q3y, w.q0x, w.q0y);
+        const float d1 = det2(q3x, q3y, w.q1x, w.q1y);
+        const float d2 = det2(q3x, q3y, w.q2x, w.q2y);
+        N0 = lanes(d0 < 0.0f);
+        N1 = lanes(d1 < 0.0f);
+        P2 = lanes(d2 >= 0.0f);
+        // |det(q3, q_i)| <= eps (|q3|_1 + |q_i|_1), evaluated in full (no short
+        // circuit: branches would cost more than the tests)
+        const float es3 = pc.eps * (fabsf(q3x) + fabsf(q3y));
+        unsure = (fabsf(d0) <= fmaf(pc.eps, fabsf(w.q0x) + fabsf(w.q0y), es3)) |
+                 (fabsf(d1) <= fmaf(pc.eps, fabsf(w.q1x) + fabsf(w.q1y), es3)) |
+                 (fabsf(d2) <= fmaf(pc.eps, fabsf(w.q2x) + fabsf(w.q2y), es3));
+        if (unsure_out) *unsure_out = unsure;
+    } else {
+        N0 = lanes(det2_neg(q3x, q3y, w.q0x, w.q0y));
+        N1 = lanes(det2_neg(q3x, q3y, w.q1x, w.q1y));
+        P2 = lanes(det2_nonneg(q3x, q3y, w.q2x, w.q2y));
+    }
     uint64_t S1 = N0 & P2, S2 = N1 & ~N0;
     if (PREC) {
         int e = lane(S1) ? 1 : (lane(S2) ? 2 : 0);
-        const float s3 = fabsf(q3x) + fabsf(q3y);
-        // evaluated in full (no short circuit: branches would cost more than the tests)
-        const bool unsure =
-            (fabsf(det2(q3x, q3y, w.q0x, w.q0y)) <= pc.eps * (s3 + fabsf(w.q0x) + fabsf(w.q0y))) |
-            (fabsf(det2(q3x, q3y, w.q1x, w.q1y)) <= pc.eps * (s3 + fabsf(w.q1x) + fabsf(w.q1y))) |
-            (fabsf(det2(q3x, q3y, w.q2x, w.q2y)) <= pc.eps * (s3 + fabsf(w.q2x) + fabsf(w.q2y)));
         if (unsure) {
             e = exit_slot64(M, f, pc, w.a0, w.a1, w.a2, P);
             ++pc.n64;
@@ -928,62 +945,246 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t 
     return (b - r) + (r % X) * G + r / X;
 }
 
+// ---- precision variant ------------------------------------------------------
+//
+// A walk step whose float32 exit determinants are unsure (within eps) is decided
+// in float64; the start tet and the start face's orientation are decided in
+// float64 too.  A ray that meets an exact float64 tie -- it lies in a face plane,
+// e.g. a ray along the mesh boundary, where Algorithm 1's zero determinants leave
+// the walk undefined -- takes the closest hit by its definition instead: FP64
+// Moller-Trumbore over every constrained triangle (inclusive edges, t in
+// (0, tmax], the start face excluded, hits within 1e-12 of the nearest going to
+// the lowest id), computed by the whole wave together.  So does a ray whose
+// origin lies on the mesh boundary (within 1e-6 of the bounds) where location
+// finds no start tet.
+
+// The closest constrained triangle along one ray, by the definition; called by
+// every lane of a wave with the same ray (lanes take every 64th triangle).
+struct DefHit {
+    int32_t tri;
+    double t, u, v;
+};
+
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) x = fmin(x, __shfl_xor(x, k, 64));
+    return x;
+}
+
+__device__ __forceinline__ int32_t wave_min_i(int32_t x) {
+#pragma unroll
+    for (int k = 32; k >= 1; k >>= 1) x = min(x, __shfl_xor(x, k, 64));
+    return x;
+}
+
+// Moller-Trumbore in float64 from the float32 points; false when the line misses
+// the closed triangle or the plane is parallel.
+__device__ __forceinline__ bool mt64(const Mem& M, const int4 fv, double ox, double oy, double oz, double dx,
+                                     double dy, double dz, double& t, double& u, double& v) {
+    const float4 A = load_pt(M, uint32_t(fv.x)), B = load_pt(M, uint32_t(fv.y)), C = load_pt(M, uint32_t(fv.z));
+    const double e1x = double(B.x) - A.x, e1y = double(B.y) - A.y, e1z = double(B.z) - A.z;
+    const double e2x = double(C.x) - A.x, e2y = double(C.y) - A.y, e2z = double(C.z) - A.z;
+    const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    const double det = e1x * px + e1y * py + e1z * pz;
+    if (det == 0.0) return false;
+    const double sx = ox - A.x, sy = oy - A.y, sz = oz - A.z;
+    u = (sx * px + sy * py + sz * pz) / det;
+    const double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    v = (dx * qx + dy * qy + dz * qz) / det;
+    t = (e2x * qx + e2y * qy + e2z * qz) / det;
+    return u >= 0.0 && v >= 0.0 && u + v <= 1.0;
+}
+
+__device__ DefHit wave_closest_hit(const DevMesh& m, const Mem& M, double ox, double oy, double oz, double dx,
+                                   double dy, double dz, double tmax, int32_t exclude) {
+    const int32_t ln = int32_t(threadIdx.x & 63);
+    const int4* cfv = reinterpret_cast<const int4*>(m.cfv);
+    double best = INFINITY;
+    for (int32_t f = ln; f < m.ntri; f += 64) {
+        double t, u, v;
+        if (f != exclude && mt64(M, cfv[f], ox, oy, oz, dx, dy, dz, t, u, v) && t > 0.0 && t <= tmax)
+            best = fmin(best, t);
+    }
+    const double tmin = wave_min(best);
+    DefHit h{TM_RAY_MISS, NAN, NAN, NAN};
+    if (!(tmin < INFINITY)) return h;
+    // the lowest id among the hits within 1e-12 of the nearest
+    int32_t id = 0x7FFFFFFF;
+    for (int32_t f = ln; f < m.ntri; f += 64) {
+        double t, u, v;
+        if (f != exclude && mt64(M, cfv[f], ox, oy, oz, dx, dy, dz, t, u, v) && t > 0.0 && t <= tmax &&
+            t <= tmin + 1e-12)
+            id = min(id, f);
+    }
+    h.tri = wave_min_i(id);
+    (void)mt64(M, cfv[h.tri], ox, oy, oz, dx, dy, dz, h.t, h.u, h.v);
+    return h;
+}
+
+// Whether p lies within 1e-6 of the extent on or outside the mesh's bounds.
+__device__ __forceinline__ bool on_bounds(const DevMesh& m, float px, float py, float pz) {
+    const float p[3] = {px, py, pz};
+    float ext = 0.0f;
+    for (int a = 0; a < 3; ++a) ext = fmaxf(ext, float(m.G) / m.inv_cell[a]);
+    bool on = false;
+    for (int a = 0; a < 3; ++a) {
+        const float hi = m.lo[a] + float(m.G) / m.inv_cell[a];
+        on |= (p[a] <= m.lo[a] + 1e-6f * ext) | (p[a] >= hi - 1e-6f * ext);
+    }
+    return on;
+}
+
+// The ties of a wave's lanes (ballot), one after the other, each by the whole
+// wave; lane `tie` writes its ray's result.  Every lane of the wave must call it.
+template <bool TMAX>
+__device__ void resolve_ties(const DevMesh& m, const Mem& M, const RayArgs& r, bool tie, int64_t i, int32_t steps,
+                             int32_t n64) {
+    uint64_t T = lanes(tie);
+    while (T) {
+        const int l = __builtin_ctzll(T);
+        T &= T - 1;
+        const int64_t k = __builtin_amdgcn_readlane(int32_t(i), l);
+        const double ox = r.orig[3 * k], oy = r.orig[3 * k + 1], oz = r.orig[3 * k + 2];
+        const double dx = r.dir[3 * k], dy = r.dir[3 * k + 1], dz = r.dir[3 * k + 2];
+        const double tmax = (TMAX && r.tmax) ? double(r.tmax[k]) : INFINITY;
+        const int32_t sf = r.start_face ? r.start_face[k] : -1;
+        const DefHit h = wave_closest_hit(m, M, ox, oy, oz, dx, dy, dz, tmax, sf);
+        if (int(threadIdx.x & 63) == l) {
+            if (h.tri < 0) {
+                write_code(r, k, TM_RAY_MISS, steps, n64);
+            } else {
+                int32_t front = -1, back = -1;
+                if (r.hit_tets) {
+                    // the ray comes from the side its direction points away from
+                    const int4 fv = reinterpret_cast<const int4*>(m.cfv)[h.tri];
+                    const int4 ft = reinterpret_cast<const int4*>(m.cft)[h.tri];
+                    const float4 A = load_pt(M, uint32_t(fv.x)), B = load_pt(M, uint32_t(fv.y)),
+                                 C = load_pt(M, uint32_t(fv.z));
+                    const double e1x = double(B.x) - A.x, e1y = double(B.y) - A.y, e1z = double(B.z) - A.z;
+                    const double e2x = double(C.x) - A.x, e2y = double(C.y) - A.y, e2z = double(C.z) - A.z;
+                    const double nd = (e1y * e2z - e1z * e2y) * dx + (e1z * e2x - e1x * e2z) * dy +
+                                      (e1x * e2y - e1y * e2x) * dz;
+                    const int32_t f = nd > 0.0 ? ft.y : ft.x, b = nd > 0.0 ? ft.x : ft.y;
+                    front = f >= 0 ? m.t_new2old[f] : -1;
+                    back = b >= 0 ? m.t_new2old[b] : -1;
+                }
+                write_result(r, k, h.tri, float(h.t), float(h.u), float(h.v), front, back, steps, n64);
+            }
+        }
+    }
+}
+
+// One ray of the precision variant, up to its result or its tie.  Returns true
+// when the ray is a tie (its result then comes from resolve_ties).  DEFER (the
+// first pass of the two-pass form): the walk stops at its first unsure step
+// instead of deciding it in float64, and *deferred is set; the result is then
+// left to the second pass.
+template <bool TMAX, int LAYOUT, bool DEFER>
+__device__ __forceinline__ bool trace_prec(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, float eps,
+                                           int32_t& steps_out, int32_t& n64_out, bool* deferred) {
+    Ray s;
+    bool degen = false, lost = false;
+    steps_out = 0;
+    n64_out = 0;
+    if (!setup_ray<TMAX, LAYOUT, true>(m, M, r, i, s, eps, nullptr, &degen, &lost)) {
+        // no start tet: an origin on the boundary takes the definition (the result of
+        // setup_ray, TM_RAY_INVALID, stands otherwise)
+        if (!lost || !on_bounds(m, r.orig[3 * i], r.orig[3 * i + 1], r.orig[3 * i + 2])) return false;
+        if (DEFER) { *deferred = true; return false; }
+        return true;
+    }
+    if (degen) {
+        if (DEFER) { *deferred = true; return false; }
+        return true;
+    }
+    Prec pc{eps, r.orig[3 * i], r.orig[3 * i + 1], r.orig[3 * i + 2], 0};
+    pc.allow_degen = false;
+    // the pipelined form of walk_ray (next record loaded inside the step)
+    if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
+    Rec R = load_rec<LAYOUT>(M, s.w.next);
+    bool unsure = false;
+    while (!pc.degen && walk_on<TMAX>(s, r.max_steps)) {
+        if (DEFER) {
+            walk_step_rec<TMAX, LAYOUT, false, true, true>(M, s.f, s.g, s.w, pc, R, &R, &unsure);
+            if (unsure) break;
+        } else {
+            walk_step_rec<TMAX, LAYOUT, true, true, true>(M, s.f, s.g, s.w, pc, R, &R);
+        }
+        ++s.steps;
+    }
+    if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
+    steps_out = s.steps;
+    n64_out = pc.n64;
+    if (DEFER && unsure) { *deferred = true; return false; }
+    if (pc.degen) return true;
+    finish_ray<TMAX>(m, M, r, i, s, pc.n64);
+    return false;
+}
+
 template <bool TMAX, int LAYOUT, bool PREC, bool STEPS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? (TMAX ? 4 : 7) : 8)))
 k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds, kn.xcd_blocks)) * blockDim.x + threadIdx.x;
-    if (j >= r.n) return;
-    const int64_t i = r.perm ? int64_t(r.perm[j]) : j;
-    if (uint64_t(i) >= uint64_t(r.n)) return;   // a caller's order that is no permutation
     const Mem M = make_mem<LAYOUT>(m);
-    Ray s;
     if (!PREC) {
+        if (j >= r.n) return;
+        const int64_t i = r.perm ? int64_t(r.perm[j]) : j;
+        if (uint64_t(i) >= uint64_t(r.n)) return;   // a caller's order that is no permutation
+        Ray s;
         if (!setup_ray<TMAX, LAYOUT, false>(m, M, r, i, s, 0.0f)) return;
         walk_ray<TMAX, LAYOUT, STEPS>(M, s, r.max_steps);
         finish_ray<TMAX>(m, M, r, i, s);
         return;
     }
-    // Precision variant.  A ray whose walk meets a float64 tie is walked again
-    // from an origin moved by 1e-6 of the mesh extent towards the centre of the
-    // mesh bounds (and off the axes); the result keeps the given origin for t.
-    // Ties on the moved ray are decided by Algorithm 1's plain inequalities.
+    // precision variant: every lane stays to the end (ties are resolved by the wave)
+    const int64_t i = j < r.n ? (r.perm ? int64_t(r.perm[j]) : j) : -1;
+    const bool valid = j < r.n && uint64_t(i) < uint64_t(r.n);
     int32_t steps = 0, n64 = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        float moved[3] = {r.orig[3 * i], r.orig[3 * i + 1], r.orig[3 * i + 2]};
-        if (attempt == 1) {
-            float c[3], ext = 0.0f, len = 0.0f;
-            for (int a = 0; a < 3; ++a) {
-                const float span = float(m.G) / m.inv_cell[a];
-                ext = fmaxf(ext, span);
-                c[a] = m.lo[a] + 0.5f * span - moved[a];
-            }
-            const float tilt[3] = {0.0123f, 0.0457f, 0.0789f};
-            for (int a = 0; a < 3; ++a) len += c[a] * c[a];
-            const float il = len > 0.0f ? 1.0f / sqrtf(len) : 0.0f;
-            for (int a = 0; a < 3; ++a) moved[a] += 1e-6f * ext * (c[a] * il + tilt[a]);
-        }
-        bool degen = false, lost = false;
-        if (!setup_ray<TMAX, LAYOUT, true>(m, M, r, i, s, kn.eps, attempt ? moved : nullptr, &degen, &lost)) {
-            if (attempt == 0 && lost) continue;   // an origin on the boundary: move it inwards
-            return;
-        }
-        Prec pc{kn.eps, moved[0], moved[1], moved[2], 0};
-        pc.allow_degen = attempt == 1;
-        pc.degen = degen && attempt == 0;
-        // the pipelined form of walk_ray (next record loaded inside the step)
-        if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
-        Rec R = load_rec<LAYOUT>(M, s.w.next);
-        while (!pc.degen && walk_on<TMAX>(s, r.max_steps - steps)) {
-            walk_step_rec<TMAX, LAYOUT, true, true, true>(M, s.f, s.g, s.w, pc, R, &R);
-            ++s.steps;
-        }
-        if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
-        steps += s.steps;
-        n64 += pc.n64;
-        if (!pc.degen) break;
+    const bool tie = valid && trace_prec<TMAX, LAYOUT, false>(m, M, r, i, kn.eps, steps, n64, nullptr);
+    resolve_ties<TMAX>(m, M, r, tie, i, steps, n64);
+}
+
+// Two-pass precision variant, first pass: the float32 walk with the unsure test
+// at the plain kernel's occupancy; a ray whose walk meets an unsure step (or
+// whose start is a float64 tie) is appended to a list -- one atomic per wave, the
+// lanes' slots from their rank in the ballot -- and left unwritten.
+template <bool TMAX, int LAYOUT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_trace_defer(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn, uint32_t* count, int32_t* list) {
+    const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds, kn.xcd_blocks)) * blockDim.x + threadIdx.x;
+    const Mem M = make_mem<LAYOUT>(m);
+    const int64_t i = j < r.n ? (r.perm ? int64_t(r.perm[j]) : j) : -1;
+    const bool valid = j < r.n && uint64_t(i) < uint64_t(r.n);
+    bool deferred = false;
+    int32_t steps = 0, n64 = 0;
+    if (valid) (void)trace_prec<TMAX, LAYOUT, true>(m, M, r, i, kn.eps, steps, n64, &deferred);
+    const uint64_t D = lanes(deferred);
+    if (D) {
+        uint32_t base = 0;
+        if ((threadIdx.x & 63) == uint32_t(__builtin_ctzll(D))) base = atomicAdd(count, uint32_t(__popcll(D)));
+        base = __builtin_amdgcn_readlane(base, __builtin_ctzll(D));
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(D >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(D), 0u));
+        if (deferred) list[base + rank] = int32_t(i);
     }
-    s.steps = steps;
-    finish_ray<TMAX>(m, M, r, i, s, n64);
+}
+
+// Second pass: the precision variant on the listed rays (count read on the
+// device), in a grid-stride loop whose trip count is the same for every lane of
+// a wave (ties are resolved by whole waves).
+template <bool TMAX, int LAYOUT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TMAX ? 4 : 7)))
+k_trace_listed(DevMesh m, RayArgs r, Knobs kn, const uint32_t* count, const int32_t* list) {
+    const Mem M = make_mem<LAYOUT>(m);
+    const int64_t n = *count;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t base = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
+        const int64_t j = base + (threadIdx.x & 63);
+        const int64_t i = j < n ? int64_t(list[j]) : -1;
+        const bool valid = j < n && uint64_t(i) < uint64_t(r.n);
+        int32_t steps = 0, n64 = 0;
+        const bool tie = valid && trace_prec<TMAX, LAYOUT, false>(m, M, r, i, kn.eps, steps, n64, nullptr);
+        resolve_ties<TMAX>(m, M, r, tie, i, steps, n64);
+    }
 }
 
 // Persistent lanes: lane g of the grid owns the rays at positions g, g + L,
@@ -1057,6 +1258,207 @@ k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs, uint32_t xcds) {
     finish_ray<true>(m, M, r, i, s, 0);
 }
 
+// Persistent waves draining a work queue (one launch over one or many jobs).
+// The ray order of every job is cut into chunks of q.chunk rays (rays per wave
+// fetch), numbered over all jobs in table order and split into q.xcds
+// contiguous ranges, one per accelerator die: block b runs on die b mod X (the
+// dispatcher deals blocks to the dies round-robin), so the waves of a die take
+// their chunks from its own range first -- neighbouring chunks then share that
+// die's L2 -- through an atomic counter per range, and take chunks from the
+// other dies' ranges once theirs is exhausted, so no die idles while work is
+// left.
+// A wave stages the ray ids of its chunk in LDS, 64 at a time (its ray queue).
+// Lanes walk one ray each; once q.refill of them have finished (a ballot), those
+// write their results and take the next rays from the queue: each needy lane's
+// rank among the needy lanes (mbcnt of the ballot) indexes the queue, so the
+// wave's rays stay packed in its lanes with no lane-to-lane exchange.
+// Registers: across a refill the lanes' ray frames, 2-D face points and tmax go
+// to LDS (one 64-lane row per word, so the stores and loads are conflict-free),
+// so that set-up does not stack its registers on top of the walk state; the
+// kernel then fits 64 VGPRs and 8 waves per SIMD like the one-lane-per-ray
+// kernel.
+// A wave moves to a chunk of another job (another mesh) only when all its
+// lanes are idle: the buffer descriptors of a step are wave-wide.  Every wave
+// ends when all ranges are exhausted and its lanes are idle.
+constexpr int kQWaves = 4;     // waves per 256-thread block
+
+template <bool TMAX>
+constexpr int stash_words() { return TMAX ? 19 : 14; }
+
+__device__ __forceinline__ int job_of_chunk(const Job* __restrict__ jobs, int n_jobs, uint32_t c) {
+    int lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (uint64_t(jobs[mid].qchunk0) <= c) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// The stashed part of a ray's state: word k of lane l at S[64 k + l].
+template <bool TMAX>
+__device__ __forceinline__ void stash_put(float* S, uint32_t l, const Ray& s) {
+    float* p = S + l;
+    p[0] = s.f.ux; p[64] = s.f.uy; p[128] = s.f.uz; p[192] = s.f.vx; p[256] = s.f.vy; p[320] = s.f.vz;
+    p[384] = s.f.pox; p[448] = s.f.poy;
+    p[512] = s.w.q0x; p[576] = s.w.q0y; p[640] = s.w.q1x; p[704] = s.w.q1y; p[768] = s.w.q2x; p[832] = s.w.q2y;
+    if (TMAX) {
+        p[896] = s.g.gx; p[960] = s.g.gy; p[1024] = s.g.gz; p[1088] = s.g.go; p[1152] = s.tmax;
+    }
+}
+
+template <bool TMAX>
+__device__ __forceinline__ void stash_get(const float* S, uint32_t l, Ray& s) {
+    const float* p = S + l;
+    s.f.ux = p[0]; s.f.uy = p[64]; s.f.uz = p[128]; s.f.vx = p[192]; s.f.vy = p[256]; s.f.vz = p[320];
+    s.f.pox = p[384]; s.f.poy = p[448];
+    s.w.q0x = p[512]; s.w.q0y = p[576]; s.w.q1x = p[640]; s.w.q1y = p[704]; s.w.q2x = p[768]; s.w.q2y = p[832];
+    if (TMAX) {
+        s.g.gx = p[896]; s.g.gy = p[960]; s.g.gz = p[1024]; s.g.go = p[1088]; s.tmax = p[1152];
+    } else {
+        s.tmax = INFINITY;
+    }
+}
+
+// Keeps the compiler from holding values loaded before this point in registers
+// past it: the job's descriptors are then loaded where set-up and results use
+// them, and only the step's buffer descriptors stay in scalar registers through
+// the walk.
+__device__ __forceinline__ void reload_point() { asm volatile("" ::: "memory"); }
+
+template <bool TMAX, int LAYOUT, bool STEPS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_trace_queue(const Job* __restrict__ jobs, int32_t n_jobs, Queue q) {
+    __shared__ float stash[kQWaves][stash_words<TMAX>() * 64];
+    __shared__ int32_t qbuf[kQWaves][64];
+    float* S = stash[threadIdx.x >> 6];
+    int32_t* Q = qbuf[threadIdx.x >> 6];
+    const uint32_t ln = threadIdx.x & 63u;
+    const uint32_t X = q.xcds;
+    const uint32_t home = blockIdx.x % X;
+    // wave-uniform state
+    uint32_t visit = 0;            // ranges visited so far (home first)
+    int job = -1;                  // the job of the rays in the lanes and the queue
+    int64_t cbase = 0;             // the current chunk: rays cbase + (cn .. ce-1) of the job
+    uint32_t cn = 0, ce = 0;
+    uint32_t qn = 0, qe = 0;       // staged queue: positions qn .. qe-1 of Q
+    uint32_t held = 0xFFFFFFFFu;   // a chunk of another job, taken while lanes were busy
+    bool exhausted = false;
+    // lane state
+    Ray s;
+    Rec R;
+    int64_t i = 0;
+    bool has = false, done = false;
+    for (;;) {
+        reload_point();
+        if (done) {
+            const Job& J = jobs[__builtin_amdgcn_readfirstlane(job)];
+            const Mem M = make_mem<LAYOUT>(J.m);
+            if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
+            if (!STEPS) s.steps = 0;
+            finish_ray<TMAX>(J.m, M, J.r, i, s);
+            has = false;
+            done = false;
+        }
+        stash_put<TMAX>(S, ln, s);
+        // refill the idle lanes
+        for (;;) {
+            const uint64_t need = lanes(!has);
+            if (need == 0 || exhausted) break;
+            reload_point();
+            if (qn == qe) {
+                if (cn == ce) {
+                    uint32_t c = held;
+                    if (c == 0xFFFFFFFFu) {
+                        // the next chunk: from the home range, else the next range that has one
+                        c = q.n_chunks;
+                        while (visit < X) {
+                            const uint32_t x = (home + visit) % X;
+                            const uint32_t lo = uint32_t(uint64_t(q.n_chunks) * x / X);
+                            const uint32_t hi = uint32_t(uint64_t(q.n_chunks) * (x + 1) / X);
+                            uint32_t k = 0;
+                            if (ln == 0) k = atomicAdd(q.cursor + 32 * x, 1u);
+                            k = __builtin_amdgcn_readfirstlane(k);
+                            if (lo + k < hi) { c = lo + k; break; }
+                            ++visit;
+                        }
+                        if (c >= q.n_chunks) { exhausted = true; break; }
+                    }
+                    const int jb = job_of_chunk(jobs, n_jobs, c);
+                    if (jb != job) {
+                        // another mesh: only once every lane of the wave is idle
+                        if (~need != 0) { held = c; break; }
+                        job = __builtin_amdgcn_readfirstlane(jb);
+                    }
+                    held = 0xFFFFFFFFu;
+                    cbase = (int64_t(c) - jobs[job].qchunk0) * q.chunk;
+                    cn = 0;
+                    ce = uint32_t(min<int64_t>(q.chunk, jobs[job].r.n - cbase));
+                }
+                // stage the next 64 rays of the chunk
+                const uint32_t cnt = min(64u, ce - cn);
+                if (ln < cnt) {
+                    const int64_t j = cbase + cn + ln;
+                    const int32_t* perm = jobs[job].r.perm;
+                    Q[ln] = perm ? perm[j] : int32_t(j);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                cn += cnt;
+                qn = 0;
+                qe = cnt;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // the needy lanes take the next positions, in lane order
+            const uint32_t take = min(uint32_t(__popcll(need)), qe - qn);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(need >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo(uint32_t(need), 0u));
+            if (!has && rank < take) {
+                const Job& J = jobs[__builtin_amdgcn_readfirstlane(job)];
+                const Mem M = make_mem<LAYOUT>(J.m);
+                i = Q[qn + rank];
+                Ray t;
+                if (uint64_t(i) < uint64_t(J.r.n) && setup_ray<TMAX, LAYOUT, false>(J.m, M, J.r, i, t, 0.0f)) {
+                    has = true;
+                    if (LAYOUT == kTet16) t.w.cur ^= int32_t(t.w.next);   // the LINK form of the step
+                    stash_put<TMAX>(S, ln, t);
+                    s.w = t.w;
+                    s.steps = t.steps;
+                    R = load_rec<LAYOUT>(M, s.w.next);
+                }
+            }
+            qn += take;
+        }
+        if (lanes(has) == 0) {
+            if (exhausted || held == 0xFFFFFFFFu) break;
+            continue;   // switch to the held chunk's job
+        }
+        stash_get<TMAX>(S, ln, s);
+        const Job& JW = jobs[__builtin_amdgcn_readfirstlane(job)];
+        const Mem M = make_mem<LAYOUT>(JW.m);
+        const int32_t max_steps = JW.r.max_steps;
+        // walk until q.refill lanes have finished (or none is left walking)
+        for (;;) {
+            const bool go = has && !done && walk_on<TMAX>(s, max_steps);
+            done = done || (has && !go);
+            const uint64_t G = lanes(go);
+            if (G == 0 || __popcll(lanes(done)) >= uint32_t(q.refill)) break;
+            if (go) {
+                Prec pc{0.0f, 0.0f, 0.0f, 0.0f, 0};
+                walk_step_rec<TMAX, LAYOUT, false, true, true>(M, s.f, s.g, s.w, pc, R, &R);
+                ++s.steps;
+            }
+        }
+    }
+}
+
+// One job entry written on the device (the single-mesh form of the queue kernel
+// reads its mesh and rays from a one-entry table like a batch).
+__global__ void k_put_job(Job j, Job* dst) { *dst = j; }
+
+__global__ void k_zero(uint32_t* p, int32_t n) {
+    const int k = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k < n) p[k] = 0u;
+}
+
 template <int LAYOUT>
 __global__ void __launch_bounds__(256) k_locate(DevMesh m, int64_t n, const float* pts, int32_t* out,
                                                 int32_t max_steps) {
@@ -1073,11 +1475,35 @@ __global__ void __launch_bounds__(256) k_locate(DevMesh m, int64_t n, const floa
     out[i] = t >= 0 ? m.t_new2old[t] : (t == TM_RAY_STEP_CAP ? -2 : -1);
 }
 
+// The persistent-wave kernel: its counters zeroed (a kernel, so the pair can be
+// captured in a graph), then a grid that fills every CU at 8 waves per SIMD (or
+// fewer blocks, when there are fewer chunks than waves).
+template <bool TMAX, int LAYOUT>
+void launch_queue_t(const Job* jobs, int32_t n_jobs, const Queue& q, bool steps, int32_t cus, hipStream_t s) {
+    if (q.n_chunks == 0) return;
+    const int32_t words = int32_t(32 * q.xcds);
+    hipLaunchKernelGGL(k_zero, dim3(unsigned((words + 255) / 256)), dim3(256), 0, s, q.cursor, words);
+    const int64_t full = int64_t(std::max(1, cus)) * (8 * 4 * 64 / 256);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(full, (int64_t(q.n_chunks) + kQWaves - 1) / kQWaves));
+    if (steps)
+        hipLaunchKernelGGL((k_trace_queue<TMAX, LAYOUT, true>), dim3(unsigned(grid)), dim3(256), 0, s, jobs, n_jobs, q);
+    else
+        hipLaunchKernelGGL((k_trace_queue<TMAX, LAYOUT, false>), dim3(unsigned(grid)), dim3(256), 0, s, jobs, n_jobs, q);
+}
+
 template <bool TMAX, int LAYOUT>
 void launch_trace_t(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s) {
     const int block = (c.block == 64 || c.block == 128) ? c.block : 256;
     const int64_t simple_grid = (r.n + block - 1) / block;
-    if (c.kernel == 2) {
+    if (c.kernel == 3) {
+        // a one-entry job table in the workspace, beside the queue's counters
+        Job j{};
+        j.m = m;
+        j.r = r;
+        Job* table = c.queue_job;
+        hipLaunchKernelGGL(k_put_job, dim3(1), dim3(1), 0, s, j, table);
+        launch_queue_t<TMAX, LAYOUT>(table, 1, c.queue, r.steps != nullptr, c.cus, s);
+    } else if (c.kernel == 2) {
         // enough lanes to fill every CU with `waves_per_simd` waves per SIMD
         const int64_t blocks_per_cu = int64_t(c.waves_per_simd) * 4 * 64 / block;
         int64_t grid = std::min<int64_t>(simple_grid, std::max<int64_t>(1, c.cus * blocks_per_cu));
@@ -1085,6 +1511,18 @@ void launch_trace_t(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipS
         const int32_t refill = std::min(64, std::max(1, c.refill));
         hipLaunchKernelGGL((k_trace_persistent<TMAX, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s,
                            m, r, refill);
+    } else if (c.eps > 0.0f && c.defer_count) {
+        // two passes: the float32 walk defers its unsure rays to a list, which the
+        // float64-capable kernel then traces (a grid that fills the device at its
+        // occupancy, reading the list's length on the device)
+        const Knobs kn{c.eps, uint32_t(c.xcd_blocks)};
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, c.defer_count, 1);
+        hipLaunchKernelGGL((k_trace_defer<TMAX, LAYOUT>), dim3(unsigned(simple_grid)), dim3(block), 0, s, m, r,
+                           uint32_t(std::max(1, c.xcds)), kn, c.defer_count, c.defer_list);
+        const int64_t full = int64_t(std::max(1, c.cus)) * (TMAX ? 4 : 7) * 4 * 64 / 256;
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(full, (r.n + 255) / 256));
+        hipLaunchKernelGGL((k_trace_listed<TMAX, LAYOUT>), dim3(unsigned(grid)), dim3(256), 0, s, m, r, kn,
+                           c.defer_count, c.defer_list);
     } else if (c.eps > 0.0f) {
         hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, true, true>), dim3(unsigned(simple_grid)), dim3(block), 0,
                            s, m, r, uint32_t(std::max(1, c.xcds)), Knobs{c.eps, uint32_t(c.xcd_blocks)});
@@ -1135,6 +1573,19 @@ hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_b
     else if (layout == kTet32N) launch_trace_batch_t<kTet32N>(d_jobs, n_jobs, g, b, X, steps, s);
     else if (layout == kTet32) launch_trace_batch_t<kTet32>(d_jobs, n_jobs, g, b, X, steps, s);
     else launch_trace_batch_t<kTet20>(d_jobs, n_jobs, g, b, X, steps, s);
+    return hipGetLastError();
+}
+
+int64_t queue_workspace_bytes() { return kQueueCursorBytes + (int64_t(sizeof(Job)) + 255) / 256 * 256; }
+
+hipError_t launch_trace_batch_queue(const Job* d_jobs, int32_t n_jobs, const Queue& q, int32_t layout,
+                                    bool steps, int32_t cus, hipStream_t s) {
+    if (n_jobs <= 0 || q.n_chunks == 0) return hipSuccess;
+    // batches carry tmax for every job (+inf where a job has none)
+    if (layout == kTet16) launch_queue_t<true, kTet16>(d_jobs, n_jobs, q, steps, cus, s);
+    else if (layout == kTet32N) launch_queue_t<true, kTet32N>(d_jobs, n_jobs, q, steps, cus, s);
+    else if (layout == kTet32) launch_queue_t<true, kTet32>(d_jobs, n_jobs, q, steps, cus, s);
+    else launch_queue_t<true, kTet20>(d_jobs, n_jobs, q, steps, cus, s);
     return hipGetLastError();
 }
 

@@ -189,9 +189,13 @@ def config_mesh(name: str) -> KuhnMesh:
       at the cube centre.
     * ``paper``: n = 128 (12,582,912 tets), jitter 0.1 cell seed 1, union of 20
       spheres (centres U[0.15, 0.85]^3, radii U[0.03, 0.12], seed 2).
+    * ``paper160``: the same scene on a finer grid, n = 160 (24,576,000 tets, whose
+      records and points no longer fit the GPU's 256 MB last-level cache).
     """
     if name == "tiny":
         return kuhn_mesh(16, jitter=0.1, seed=0)
     if name == "paper":
         return kuhn_mesh(128, jitter=0.1, seed=1, spheres=random_spheres(20, seed=2))
+    if name == "paper160":
+        return kuhn_mesh(160, jitter=0.1, seed=1, spheres=random_spheres(20, seed=2))
     raise KeyError(name)

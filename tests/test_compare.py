@@ -87,3 +87,19 @@ def test_hit_beyond_tmax_and_t_error(tiny_mesh, tiny_oracle):
     got["tri"][hit[7]] = -2
     rep = compare(tiny_mesh.points, tiny_oracle.tri_verts, o, d, ref, got, min_identical=0.0)
     assert rep["gpu_abort_or_invalid"] == 1 and rep["n_unexplained"] == 1
+
+
+def test_t_tolerances(tiny_mesh, tiny_oracle):
+    """A matched hit's t: within t_rtol * t passes, beyond it fails; an absolute
+    allowance (per ray) widens the bound by exactly that much."""
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.05), 32, 32, 60.0)
+    ref = tiny_oracle.trace(o, d)
+    i = int(np.nonzero(ref["tri"] >= 0)[0][7])
+    for shift, atol, ok in ((0.5e-5, 0.0, True), (2e-5, 0.0, False), (2e-5, 2e-5 * ref["t"][i], True),
+                            (4e-5, 2e-5 * ref["t"][i], False)):
+        got = _copy(ref)
+        got["t"][i] = ref["t"][i] * (1.0 + shift)
+        at = np.zeros(len(o))
+        at[i] = atol
+        rep = compare(tiny_mesh.points, tiny_oracle.tri_verts, o, d, ref, got, t_atol=at)
+        assert rep["ok"] == ok, (shift, atol, rep["max_t_rel"])

@@ -102,11 +102,17 @@ def _fill(jobs):
         j["out"]["steps"].fill_(-9)
 
 
-@pytest.mark.parametrize("block", [64, 128, 256])
-def test_batch_matches_single(tetrt, scenes, uploaded, block):
+@pytest.mark.parametrize("kw", [dict(block=64), dict(block=128), dict(block=256), dict(kernel=3),
+                                dict(kernel=3, queue_chunk=64, refill=1), dict(kernel=3, queue_chunk=1024, refill=64),
+                                dict(kernel=3, xcds=1, sort=2, sort_chunk_log2=10)])
+def test_batch_matches_single(tetrt, scenes, uploaded, kw):
+    """Every job's results equal trace_closest on its own mesh, bit for bit: the
+    one-lane-per-ray batch kernel at each block size, and the persistent waves
+    draining one queue over all jobs (rays per fetch, refill threshold, one range
+    or one per XCD)."""
     jobs = _jobs(tetrt, scenes, uploaded)
     b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))
-    b.set(jobs, block=block)
+    b.set(jobs, **kw)
     _fill(jobs)
     b.launch()
     for k, j in enumerate(jobs):
@@ -157,11 +163,12 @@ def test_batch_binned(tetrt, scenes, uploaded, chunk):
     b.free()
 
 
-def test_batch_graph_replays(tetrt, scenes, uploaded):
+@pytest.mark.parametrize("kernel", [1, 3])
+def test_batch_graph_replays(tetrt, scenes, uploaded, kernel):
     jobs = _jobs(tetrt, scenes, uploaded)
     cap = sum(int(j["orig"].shape[0]) for j in jobs)
     b = tetrt.Batch(max_jobs=len(jobs), max_rays=cap)
-    b.set(jobs, sort=2, sort_chunk_log2=10)
+    b.set(jobs, sort=2, sort_chunk_log2=10, kernel=kernel)
     want = [_single(j) for j in jobs]
     for rep in range(3):
         _fill(jobs)
@@ -173,14 +180,14 @@ def test_batch_graph_replays(tetrt, scenes, uploaded):
             _same(_host(j["out"]), want[k], "replay %d job %d" % (rep, k))
     # same shape, other rays: the captured graph reads the new table
     jobs2 = _jobs(tetrt, scenes, uploaded, reverse=True)
-    b.set(jobs2, sort=2, sort_chunk_log2=10)
+    b.set(jobs2, sort=2, sort_chunk_log2=10, kernel=kernel)
     _fill(jobs2)
     b.graph_launch()
     for k, j in enumerate(jobs2):
         _same(_host(j["out"]), _single(j), "new table job %d" % k)
     # another shape: fewer jobs, binning off -> captured again
     jobs3 = jobs2[:4]
-    b.set(jobs3, sort=1)
+    b.set(jobs3, sort=1, kernel=kernel)
     _fill(jobs3)
     b.graph_launch()
     for k, j in enumerate(jobs3):
@@ -193,7 +200,11 @@ def test_batch_tune(tetrt, scenes, uploaded):
     b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))
     b.set(jobs)
     chosen, ms = b.tune(reps=2)
-    assert chosen["block"] in (64, 128, 256) and chosen["sort"] in (1, 2) and ms > 0
+    assert chosen["kernel"] in (1, 3) and chosen["sort"] in (1, 2) and ms > 0
+    if chosen["kernel"] == 1:
+        assert chosen["block"] in (64, 128, 256)
+    else:
+        assert chosen["queue_chunk"] in (64, 256, 1024) and chosen["refill"] in (8, 32)
     _fill(jobs)
     b.launch()
     for k, j in enumerate(jobs):
@@ -216,6 +227,8 @@ def test_batch_errors(tetrt, scenes, uploaded):
         b.set(jobs, eps=1e-6)
     with pytest.raises(tetrt.TetRTError, match="one lane per ray"):
         b.set(jobs, kernel=2)
+    with pytest.raises(tetrt.TetRTError, match="queue_chunk"):
+        b.set(jobs, kernel=3, queue_chunk=96)
     with pytest.raises(tetrt.TetRTError, match="n_jobs"):
         b.set(jobs + jobs)
     small = tetrt.Batch(max_jobs=len(jobs), max_rays=n - 1)
@@ -232,3 +245,48 @@ def test_batch_errors(tetrt, scenes, uploaded):
     small.free()
     b.free()
     other.free()
+
+
+def test_batch_full_size_sampled_oracle(tetrt):
+    """The many-mesh workload at its sizes: the largest mesh of the 64-mesh set
+    (n = 88, 4.1M tets) with its whole ray budget, beside a small and a middle
+    one, in one batched launch (Tet16, the benchmark's layout); AO rays from the
+    oracle's camera hits.  20,000 sampled rays per job against the oracle."""
+    from _oracle_threads import oracle_trace
+    specs = batch_specs(count=64, seed=10)
+    order = np.argsort([s["n"] for s in specs])
+    pick = [int(order[-1]), int(order[0]), int(order[len(order) // 2])]
+    assert specs[pick[0]]["n"] == 88
+    rng = np.random.default_rng(90)
+    scenes, jobs, meshes = [], [], []
+    for k in pick:
+        spec = specs[k]
+        m = spec_mesh(spec)
+        om = oracle.OracleMesh.from_kuhn(m)
+        po, pd = camera_rays(spec)
+        pref = oracle_trace(om, po, pd)
+        ao, ad, atm, sf = ao_from_hits(m.points, lambda ids: om.tri_verts[ids], po, pd, pref["tri"],
+                                       pref["t"], spec["rays"] - len(po), spec["ao_seed"])
+        o, d = np.concatenate([po, ao]), np.concatenate([pd, ad])
+        tmax = np.concatenate([np.full(len(po), np.inf, np.float32), atm])
+        sfc = np.concatenate([np.full(len(po), -1, np.int32), sf])
+        mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout="tet16")
+        meshes.append(mesh)
+        jobs.append(dict(mesh=mesh, orig=_dev(o), dirs=_dev(d), tmax=_dev(tmax), start_face=_dev(sfc),
+                         out=tetrt.outputs(len(o), "cuda:0")))
+        scenes.append((m, om, o, d, tmax, sfc))
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))
+    b.set(jobs)
+    b.launch()
+    for (m, om, o, d, tmax, sfc), j, k in zip(scenes, jobs, pick):
+        got = _host(j["out"])
+        n = len(o)
+        idx = np.sort(rng.choice(n, min(n, 20000), replace=False))
+        ref = oracle_trace(om, o[idx], d[idx], tmax[idx], start_face=sfc[idx])
+        rep = compare(m.points, om.tri_verts, o[idx], d[idx], ref, {x: v[idx] for x, v in got.items()},
+                      tmax=tmax[idx])
+        assert rep["ok"], (specs[k]["n"], n, rep)
+        assert not np.any(got["tri"] <= -2)
+    b.free()
+    for mm in meshes:
+        mm.free()

@@ -86,6 +86,12 @@ def test_primary_benchmark_kernel_identical(paper):
     torch.cuda.synchronize()
     for k, v in res.items():
         assert np.array_equal(v.cpu().numpy(), got[k], equal_nan=True), k
+    # ... and by persistent waves draining the queue (per-XCD ranges, the default
+    # rays per fetch and refill)
+    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), start_tet=start, kernel=3)
+    torch.cuda.synchronize()
+    for k, v in res.items():
+        assert np.array_equal(v.cpu().numpy(), got[k], equal_nan=True), ("queue", k)
 
 
 def test_primary_sampled_vs_oracle(paper):
@@ -128,12 +134,14 @@ def test_ao_sampled_vs_oracle(paper):
     rep = compare(m.points, om.tri_verts, ao, ad, ref, g, tmax=atm)
     assert rep["ok"], rep
     _check_properties(m, mesh, ao, ad, g, atm)
-    # the benchmark's kernel (no step counts or tet ids) gives the same results
-    res = mesh.trace(torch.from_numpy(ao).cuda(), torch.from_numpy(ad).cuda(),
-                     tmax=torch.from_numpy(atm).cuda(), start_face=torch.from_numpy(sf).cuda(), sort=2)
-    torch.cuda.synchronize()
-    for k, v in res.items():
-        assert np.array_equal(v.cpu().numpy(), g[k], equal_nan=True), k
+    # the benchmark's kernel (no step counts or tet ids) gives the same results, and
+    # so do persistent waves draining the queue of the binned rays
+    for kw in (dict(), dict(kernel=3)):
+        res = mesh.trace(torch.from_numpy(ao).cuda(), torch.from_numpy(ad).cuda(),
+                         tmax=torch.from_numpy(atm).cuda(), start_face=torch.from_numpy(sf).cuda(), sort=2, **kw)
+        torch.cuda.synchronize()
+        for k, v in res.items():
+            assert np.array_equal(v.cpu().numpy(), g[k], equal_nan=True), (kw, k)
     # the precision variant on the same rays meets the same bar
     res = mesh.trace(torch.from_numpy(ao).cuda(), torch.from_numpy(ad).cuda(),
                      tmax=torch.from_numpy(atm).cuda(), start_face=torch.from_numpy(sf).cuda(), sort=2,
@@ -163,3 +171,44 @@ def test_ao_from_device_hits_properties(paper):
     g2 = {k: v.cpu().numpy() for k, v in mesh.trace(A[0], A[1], tmax=A[2], start_face=A[3]).items()}
     for k in g:
         assert np.array_equal(g[k], g2[k], equal_nan=True), k
+
+
+def test_finer_grid_sampled_vs_oracle():
+    """The same scene on a 160^3 grid (24.6M tets: Tet16 records and points are
+    442 MB, past the 256 MB last-level cache), in the benchmark's launch
+    configuration: 10,000 sampled primary rays and the AO rays of 2,000 of them
+    against the oracle, every ray by properties."""
+    import paper_2103_02309_amd as tetrt
+    from synth import config_mesh
+    from _oracle_threads import oracle_trace
+    m = config_mesh("paper160")
+    om = oracle.OracleMesh.from_kuhn(m)
+    o, d, _ = pinhole_rays((0.5, 0.5, 0.02), 1920, 1080, 60.0, tile=8)
+    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout="tet16")
+    assert mesh.info["hot_bytes"] > 256e6
+    try:
+        res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), want_steps=True)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in res.items()}
+        _check_properties(m, mesh, o, d, got)
+        rng = np.random.default_rng(16)
+        idx = np.sort(rng.choice(o.shape[0], 10000, replace=False))
+        cam = om.locate(o[:1])
+        ref = oracle_trace(om, o[idx], d[idx], start_tet=np.full(idx.shape[0], cam[0], np.int32))
+        rep = compare(m.points, om.tri_verts, o[idx], d[idx], ref, {k: v[idx] for k, v in got.items()})
+        assert rep["ok"], rep
+        sub = idx[:2000]
+        hit = ref["tri"][:2000] >= 0
+        hp = o[sub][hit].astype(np.float64) + ref["t"][:2000][hit, None] * d[sub][hit].astype(np.float64)
+        nrm, _ = tri_geometry(m.points, om.tri_verts[ref["tri"][:2000][hit]])
+        ao, ad, atm, parent = ao_rays(hp, nrm, d[sub][hit], k=8, seed=3, tmax=0.1)
+        sf = ref["tri"][:2000][hit][parent].astype(np.int32)
+        res = mesh.trace(torch.from_numpy(ao).cuda(), torch.from_numpy(ad).cuda(),
+                         tmax=torch.from_numpy(atm).cuda(), start_face=torch.from_numpy(sf).cuda(), sort=2)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in res.items()}
+        ref_a = oracle_trace(om, ao, ad, atm, start_face=sf)
+        rep = compare(m.points, om.tri_verts, ao, ad, ref_a, g, tmax=atm)
+        assert rep["ok"], rep
+    finally:
+        mesh.free()

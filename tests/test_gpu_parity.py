@@ -49,6 +49,7 @@ def _ao_from(m, om, o, d, ref, k=8, seed=3, tmax=0.1):
 
 
 KERNELS = [dict(kernel=1), dict(kernel=2), dict(kernel=2, grid_cap=2, refill=8),
+           dict(kernel=3), dict(kernel=3, queue_chunk=64, refill=1, xcds=1),
            dict(eps=1e-6), dict(eps=1e-4)]   # the last two: the precision variant
 
 
@@ -222,8 +223,11 @@ def test_repeat_calls_identical(tiny):
     assert np.array_equal(a["t"], b["t"], equal_nan=True)
 
 
-@pytest.mark.parametrize("refill", [1, 16, 64])
-def test_persistent_matches_one_lane_per_ray(tiny, refill):
+@pytest.mark.parametrize("kw", [dict(kernel=2, grid_cap=3, refill=1), dict(kernel=2, grid_cap=3, refill=16),
+                                dict(kernel=2, grid_cap=3, refill=64), dict(kernel=3),
+                                dict(kernel=3, queue_chunk=64, refill=1), dict(kernel=3, queue_chunk=4096, refill=64),
+                                dict(kernel=3, queue_chunk=128, refill=5, xcds=3)])
+def test_persistent_matches_one_lane_per_ray(tiny, kw):
     """Persistent lanes (few blocks, so every lane takes many rays) give
     bit-identical results to one lane per ray: same arithmetic per ray."""
     m, om, mesh = tiny
@@ -235,7 +239,7 @@ def test_persistent_matches_one_lane_per_ray(tiny, refill):
     a = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), start_tet=_dev(st), want_tets=True,
                          want_steps=True, kernel=1))
     b = _host(mesh.trace(_dev(o), _dev(d), tmax=_dev(tm), start_tet=_dev(st), want_tets=True,
-                         want_steps=True, kernel=2, grid_cap=3, refill=refill))
+                         want_steps=True, **kw))
     for k in a:
         assert np.array_equal(a[k], b[k], equal_nan=True), k
 
@@ -273,7 +277,8 @@ def test_hot_bytes_per_layout(tetrt, tiny_mesh, layout, rec_bytes):
 @pytest.mark.parametrize("kw", [dict(sort=2), dict(sort=2, sort_cells_log2=2, sort_dirq=1),
                                 dict(sort=2, sort_chunk_log2=10, sort_cells_log2=7, sort_dirq=3),
                                 dict(sort=2, sort_chunk_log2=13),
-                                dict(sort=2, kernel=2, grid_cap=3, refill=8)])
+                                dict(sort=2, kernel=2, grid_cap=3, refill=8), dict(sort=2, kernel=3),
+                                dict(sort=2, kernel=3, queue_chunk=64, refill=2)])
 def test_binned_rays_match_unbinned(tiny, kw):
     """Tracing in bin order through the permutation changes no result, and the
     results stay at the caller's positions."""
@@ -415,9 +420,36 @@ def test_handle_workspace_and_no_workspace(tiny_mesh, tetrt):
                 assert np.array_equal(got[k], ref[k], equal_nan=True), k
     # more rays than the handle's workspace holds: refused when asked for
     with pytest.raises(tetrt.TetRTError, match="workspace"):
-        big = n + 256                             # past the workspace's rounding
+        big = 2 * n + 4096                        # past all the handle's workspace holds
         O2, D2 = _dev(np.resize(o, (big, 3))), _dev(np.resize(d, (big, 3)))
         _raw_trace(tetrt, ws_mesh.handle, O2, D2, _dev(np.resize(tm, big)),
                    tetrt.outputs(big, "cuda:0"), sort=2)
     plain.free()
+    ws_mesh.free()
+
+
+def test_queue_kernel_needs_a_workspace(tiny_mesh, tetrt):
+    """The queue kernel keeps its counters in a workspace: through the raw C-ABI
+    without one it is refused; with the caller's or the handle's own it runs, and
+    an order from tetmesh_bin_rays feeds its queue."""
+    m = tiny_mesh
+    mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout="tet16")
+    ws_mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout="tet16", bin_rays=10)
+    o, d = random_interior_rays(5000, 91)
+    O, D = _dev(o), _dev(d)
+    ref = _host(mesh.trace(O, D, want_steps=True))
+    out = tetrt.outputs(5000, "cuda:0", want_steps=True)
+    with pytest.raises(tetrt.TetRTError, match="queue kernel needs a workspace"):
+        _raw_trace(tetrt, mesh.handle, O, D, None, out, kernel=3)
+    _raw_trace(tetrt, ws_mesh.handle, O, D, None, out, kernel=3)
+    got = _host(out)
+    for k in ref:
+        assert np.array_equal(got[k], ref[k], equal_nan=True), k
+    order = mesh.bin_rays(O, D, sort_chunk_log2=10)
+    got = _host(mesh.trace(O, D, want_steps=True, kernel=3, order=order))
+    for k in ref:
+        assert np.array_equal(got[k], ref[k], equal_nan=True), k
+    with pytest.raises(tetrt.TetRTError, match="queue_chunk"):
+        mesh.trace(O, D, kernel=3, queue_chunk=100)
+    mesh.free()
     ws_mesh.free()

@@ -117,6 +117,13 @@ def test_secondary_rays_properties(tetrt, scene, kind):
         assert cos.min() > -1e-5
         # cosine-weighted: E[cos] = 2/3 (standard deviation of cos is sqrt(1/18))
         assert abs(cos.mean() - 2.0 / 3.0) < 5.0 * np.sqrt(1.0 / 18.0 / hit.sum())
+    # the request's ray definition restated on the host, from the same hit records
+    from synth.serve import secondary_rays
+    ho, hd, htm, hsf = secondary_rays(dict(req, kind=kind), hm.points, mesh.tri_vertices(
+        np.arange(mesh.info["n_tris"])), c0["orig"], c0["dirs"], h0["tri"], h0["t"])
+    assert np.array_equal(hsf, r1["sf"]) and np.array_equal(htm, r1["tmax"])
+    assert np.abs(ho - r1["orig"]).max() < 1e-6
+    assert np.abs(hd - r1["dirs"]).max() < 1e-5
 
 
 @pytest.mark.parametrize("kind", ["primary", "shadow", "ao"])
@@ -213,3 +220,95 @@ def test_server_errors(tetrt, scene):
         srv.submit(big, **_req(specs[0], 0, "primary", 128, 128))
     assert srv.pending() == {"queued": 0, "admitted": 0, "finished": 0}
     srv.free()
+
+
+from _oracle_threads import oracle_trace as _oracle_trace  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def served_scene(tetrt):
+    import oracle
+    big = batch_specs(count=1, seed=31, n_lo=64, n_hi=72)[0]          # n = 71: 2.1M tets
+    small = batch_specs(count=2, seed=32, n_lo=8, n_hi=20)
+    specs = [big] + small
+    hosts = [spec_mesh(s) for s in specs]
+    meshes = [tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout="tet16") for m in hosts]
+    oracles = [oracle.OracleMesh.from_kuhn(m) for m in hosts]
+    yield specs, hosts, meshes, oracles
+    for m in meshes:
+        m.free()
+
+
+def test_served_vs_oracle(tetrt, served_scene):
+    """Served results of primary, shadow and AO requests (a 1024x1024 one among
+    them, on a 2.1M-tet mesh, all in one mix) against the FP64 oracle on the rays
+    of each request's definition, generated on the host: camera rays, then the
+    secondary rays from the oracle's own camera-ray hits.  Pixels whose camera
+    ray meets the surface within 1e-6 of a triangle edge are left out of the
+    secondary comparison (several start faces are correct there)."""
+    from oracle.compare import compare, _edge_distance
+    from synth.serve import camera_rays, secondary_rays
+    specs, hosts, meshes, oracles = served_scene
+    plan = [(0, "primary", 1024, 1024), (0, "shadow", 256, 256), (0, "ao", 256, 256),
+            (1, "ao", 64, 64), (2, "shadow", 128, 64), (1, "primary", 64, 64), (2, "ao", 96, 96)]
+    reqs, outs = [], []
+    srv = tetrt.Server(meshes, max_rays=1 << 21, ring=2)
+    for q, (k, kind, W, H) in enumerate(plan):
+        r = _req(specs[k], k, kind, W, H, seed=1000 + q)
+        r["ao_tmax"] = 0.1
+        reqs.append(r)
+        outs.append(tetrt.outputs(W * H, "cuda:0"))
+        srv.submit(outs[-1], **r)
+    srv.drain()
+    assert len(srv.poll()) == len(plan)
+    srv.free()
+    rng = np.random.default_rng(77)
+    for q, (r, out) in enumerate(zip(reqs, outs)):
+        k = r["mesh"]
+        m, om = hosts[k], oracles[k]
+        got = _host(out)
+        o, d = camera_rays(r)
+        n = o.shape[0]
+        idx = np.arange(n) if n <= 65536 else np.sort(rng.choice(n, 40000, replace=False))
+        ref0 = _oracle_trace(om, o[idx], d[idx])
+        sub = {key: v[idx] for key, v in got.items()}
+        if r["kind"] == "primary":
+            rep = compare(m.points, om.tri_verts, o[idx], d[idx], ref0, sub)
+            assert rep["ok"], (q, r["kind"], rep)
+            continue
+        o1, d1, tm1, sf1 = secondary_rays(r, m.points, om.tri_verts, o[idx], d[idx], ref0["tri"], ref0["t"])
+        ref1 = _oracle_trace(om, o1, d1, tm1, start_face=sf1)
+        # camera hits on a triangle edge: the secondary ray is not defined uniquely
+        hit = ref0["tri"] >= 0
+        keep = np.ones(idx.size, bool)
+        hp = o[idx][hit].astype(np.float64) + ref0["t"][hit, None] * d[idx][hit].astype(np.float64)
+        keep[np.nonzero(hit)[0]] = _edge_distance(m.points.astype(np.float64), om.tri_verts,
+                                                  ref0["tri"][hit], hp) > 1e-6
+        assert keep.mean() > 0.995, keep.mean()
+        # The served secondary rays are built on the device from its own float32 camera
+        # hits, these from the oracle's FP64 ones: origins and directions differ by
+        # float32 rounding (about 1e-7).  That moves a hit by about 1e-7 / |cos| along
+        # its triangle and its t by as much in distance, whatever t is: t gets an
+        # absolute allowance of 1e-6 of the scene extent / |cos| (in units of the
+        # direction's length) beside its relative tolerance, and t and the weights are
+        # held to the tolerances for |cos| >= 0.1 (ids everywhere), to 100x looser
+        # bounds below.
+        P = m.points.astype(np.float64)
+        tv = om.tri_verts[np.maximum(ref1["tri"], 0)]
+        nrm = np.cross(P[tv[:, 1]] - P[tv[:, 0]], P[tv[:, 2]] - P[tv[:, 0]])
+        dd = d1.astype(np.float64)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            cos = np.abs(np.einsum("ij,ij->i", nrm, dd)) / (np.linalg.norm(nrm, axis=1) * np.linalg.norm(dd, axis=1))
+        steep = ~(ref1["tri"] >= 0) | (cos >= 0.1)
+        for sel, t_rtol, bary_tol, ident in ((keep & steep, 1e-5, 1e-4, 0.9999 if keep.sum() >= 10000 else 0.999),
+                                             (keep & ~steep, 1e-3, 1e-2, 0.99)):
+            # the allowance grows as 1 / |cos| where the ray meets its triangle obliquely
+            dl = np.linalg.norm(dd[sel], axis=1) * np.maximum(np.nan_to_num(cos[sel], nan=1.0), 1e-4)
+            rep = compare(m.points, om.tri_verts, o1[sel], d1[sel], {x: v[sel] for x, v in ref1.items()},
+                          {x: v[sel] for x, v in sub.items()}, tmax=tm1[sel], t_rtol=t_rtol, bary_tol=bary_tol,
+                          min_identical=ident, t_atol=np.where(dl > 0, 1e-6 / np.maximum(dl, 1e-30), 0.0))
+            assert rep["ok"], (q, r["kind"], rep)
+        # most rays are held to the plain tolerances
+        assert (keep & steep).sum() > 0.5 * keep.sum()
+        assert (ref1["tri"][keep] == -3).sum() == (~hit[keep]).sum()   # no camera hit: invalid
+        assert (ref1["tri"][keep] >= 0).sum() > 0.02 * keep.sum()

@@ -128,3 +128,34 @@ def test_batch_specs_ranges_and_seeding():
     # AO rays: nothing hit -> empty; otherwise count rays leaving from hit faces
     z = ao_from_hits(None, None, o, d, np.full(len(o), -1, np.int32), np.zeros(len(o), np.float32), 10, 1)
     assert all(len(x) == 0 for x in z)
+
+
+def test_served_secondary_rays_definition():
+    """Host-side served rays: the PCG hash is a permutation of 32-bit values (on a
+    2^20 sample: no collisions) and its unit numbers are uniform; shadow rays end
+    at the light (t = 1); AO rays are unit, on the incoming side of the normal, and
+    cosine-distributed (E[cos] = 2/3); pixels without a hit get a zero direction."""
+    from synth.serve import pcg_hash, unit_floats, secondary_rays
+    h = pcg_hash(np.arange(1 << 20, dtype=np.uint64))
+    assert np.unique(h).size == 1 << 20
+    u = unit_floats(h)
+    assert u.min() >= 0.0 and u.max() < 1.0 and abs(u.mean() - 0.5) < 2e-3
+    P = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+    tv = np.array([[0, 1, 2]])
+    n = 20000
+    rng = np.random.default_rng(1)
+    o = np.c_[rng.uniform(0.05, 0.3, n), rng.uniform(0.05, 0.3, n), np.full(n, 1.0)].astype(np.float32)
+    d = np.tile(np.array([[0, 0, -1]], np.float32), (n, 1))
+    tri = np.zeros(n, np.int32)
+    tri[::10] = -1
+    t = np.ones(n)
+    req = dict(kind="shadow", light=(0.5, 0.5, 3.0), ao_tmax=0.1, seed=5)
+    so, sd, stm, ssf = secondary_rays(req, P, tv, o, d, tri, t)
+    hit = tri >= 0
+    assert np.allclose(so[hit] + sd[hit], [0.5, 0.5, 3.0], atol=1e-6) and np.all(stm[hit] == 1.0)
+    assert np.all(sd[~hit] == 0) and np.all(ssf[~hit] == -1) and np.all(ssf[hit] == 0)
+    ao, ad, atm, asf = secondary_rays(dict(req, kind="ao"), P, tv, o, d, tri, t)
+    assert np.allclose(np.linalg.norm(ad[hit], axis=1), 1.0, atol=1e-6)
+    cos = ad[hit, 2].astype(np.float64)      # the normal on the incoming side is +z
+    assert cos.min() >= 0.0 and abs(cos.mean() - 2.0 / 3.0) < 5.0 * np.sqrt(1.0 / 18.0 / hit.sum())
+    assert np.all(atm[hit] == np.float32(0.1)) and np.allclose(ao[hit, 2], 0.0)
