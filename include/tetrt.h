@@ -253,6 +253,27 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
                   int32_t* d_steps, const tm_trace_opts* opts, void* hip_stream);
 
 /*
+ * trace_closest_noalloc -- trace_closest for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and errors as
+ * trace_closest, except: opts->workspace must be NULL; a trace that bins its
+ * rays (sort = 2, or the automatic rule) puts the binning permutation in a
+ * fixed array of the library instead (4 bytes per ray, at most
+ * TM_NOALLOC_MAX_BINNED_RAYS rays: more is TM_ERR_ARG).  The array exists once
+ * per device and lives until the process ends (64 MiB of device memory on every
+ * device the library's kernels have run on); it is looked up, not allocated,
+ * on a device's first call.  Every call on a device shares it, so calls that
+ * bin and overlap in time on one device (other streams, other threads) race
+ * and must be ordered by the caller.  Unbinned traces use no scratch at all.
+ */
+#define TM_NOALLOC_MAX_BINNED_RAYS (1 << 24)
+int trace_closest_noalloc(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d_dir,
+                          const float* d_tmax, const int32_t* d_start_tet,
+                          const int32_t* d_start_face, int32_t* d_tri, float* d_t, float* d_bary,
+                          int32_t* d_hit_tets, int32_t* d_steps, const tm_trace_opts* opts,
+                          void* hip_stream);
+
+/*
  * tetmesh_locate -- tet containing each point (paper, Sec. "Locating points in
  * a tetrahedral mesh": a straight-line walk from a source tet, here the seed
  * tet of the point's cell in a uniform grid over the mesh bounds).

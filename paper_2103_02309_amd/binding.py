@@ -119,6 +119,9 @@ def _load():
     L.trace_closest.restype = C.c_int
     L.trace_closest.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                 C.POINTER(_TraceOpts), vp]
+    L.trace_closest_noalloc.restype = C.c_int
+    L.trace_closest_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                        C.POINTER(_TraceOpts), vp]
     L.tetmesh_trace_workspace.restype = C.c_int
     L.tetmesh_trace_workspace.argtypes = [vp, i64, vp, C.POINTER(_TraceOpts), C.POINTER(i64)]
     L.tetmesh_bin_rays.restype = C.c_int
@@ -240,6 +243,26 @@ def trace_closest(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None, s
             _dev(steps, torch.int32, n, (), "steps", True)]
     o = _trace_opts(dict(opts), workspace, fp64_steps, n)
     _check(_load().trace_closest(C.c_void_p(handle), n, *args, C.byref(o), _stream(stream)))
+
+
+def trace_closest_noalloc(handle, orig, dirs, tri, t, bary, tmax=None, start_tet=None,
+                          start_face=None, hit_tets=None, steps=None, stream=None, **opts):
+    """trace_closest for callers that cannot allocate: binning uses the library's
+    fixed per-device array (at most TM_NOALLOC_MAX_BINNED_RAYS rays)."""
+    n = int(orig.shape[0]) if orig.dim() >= 1 else 0
+    args = [_dev(orig, torch.float32, n, (3,), "orig"), _dev(dirs, torch.float32, n, (3,), "dirs"),
+            _dev(tmax, torch.float32, n, (), "tmax", True),
+            _dev(start_tet, torch.int32, n, (), "start_tet", True),
+            _dev(start_face, torch.int32, n, (), "start_face", True),
+            _dev(tri, torch.int32, n, (), "tri"), _dev(t, torch.float32, n, (), "t"),
+            _dev(bary, torch.float32, n, (2,), "bary"),
+            _dev(hit_tets, torch.int32, n, (2,), "hit_tets", True),
+            _dev(steps, torch.int32, n, (), "steps", True)]
+    o = _trace_opts(dict(opts), None, None, n)
+    _check(_load().trace_closest_noalloc(C.c_void_p(handle), n, *args, C.byref(o), _stream(stream)))
+
+
+NOALLOC_MAX_BINNED_RAYS = 1 << 24
 
 
 def tetmesh_trace_workspace(handle, n_rays, has_tmax, **opts):

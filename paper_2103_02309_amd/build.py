@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtetrt.so")
 PROBE_LIB = os.path.join(HERE, "libtetrt_probe.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("api.cpp", "batch.cpp", "server.cpp", "pack.cpp", "walk.hip",
-                                                    "sort.hip", "serve.hip")]
+                                                    "sort.hip", "serve.hip", "noalloc.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("pack.h", "device.h", "handle.h")] + [
     os.path.join(ROOT, "include", "tetrt.h")]
 PROBE_SOURCES = [os.path.join(HERE, "csrc", "probe_l1.hip")]
