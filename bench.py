@@ -92,6 +92,7 @@ def parse():
                     help="primary rays: camera located once per pass (shared) or by every ray")
     ap.add_argument("--eps", type=float, default=0.0,
                     help="precision variant threshold for both passes (0 = plain float32 walk)")
+    ap.add_argument("--passes", type=int, default=0, help="precision variant: 2 = the two-pass form")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads for the CPU baseline (0 = the host's CPUs, at most 16)")
@@ -203,7 +204,7 @@ def main():
 
     # binning: the library's automatic rule (batches of at least 2^18 rays that carry
     # tmax), run as its own kernel so that the walk kernel is timed apart
-    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill, eps=args.eps)
+    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill, eps=args.eps, passes=args.passes)
     skw = dict(sort_chunk_log2=args.sort_chunk, sort_dirq=args.sort_dirq, sort_cells_log2=args.sort_cells)
     bin_p = args.sort == 2
     bin_a = args.sort == 2 or (args.sort == 0 and n_a >= (1 << 18))

@@ -168,7 +168,11 @@ typedef struct {
                             the call's own binning (sort is then ignored) */
     int32_t queue_chunk; /* kernel 3: rays a wave takes from the queue at a time, a multiple
                             of 64 in [64, 4096] (0 = 256) */
-    int32_t reserved;
+    int32_t passes;      /* precision variant: 0 or 1 = one pass; 2 = two passes, a float32
+                            walk that defers the rays meeting an unsure step to a list, then
+                            the float64-capable walk of the listed rays only (same results;
+                            needs a workspace, else one pass).  Measured slower than one pass
+                            on the 12.6M-tet workload */
 } tm_trace_opts;
 
 /*
@@ -338,8 +342,8 @@ int tm_batch_create(int32_t max_jobs, int64_t max_rays, tm_batch* out);
  * max_jobs), copied.  opts as for trace_closest, except: kernel 0, 1 or 3 (3:
  * persistent waves drain one queue of every job's rays, queue_chunk and refill
  * as for trace_closest; xcds = its number of per-XCD ranges, 0 = the device's
- * XCDs), eps = 0, xcd_blocks, grid_cap, workspace, fp64_steps and order are
- * ignored, with kernel 1 xcds = 0 means round-robin placement (xcds > 1: one
+ * XCDs), eps > 0 (the precision variant, one pass) with kernel 0 or 1 only,
+ * xcd_blocks, grid_cap, passes, workspace, fp64_steps and order are ignored, with kernel 1 xcds = 0 means round-robin placement (xcds > 1: one
  * contiguous range of the whole launch per XCD), and the binning chunk size is one for all jobs
  * (sort = 0 bins the jobs that carry tmax and have at least 2^18 rays).  The new table is copied to the device on
  * hip_stream, after the batch's previous table copy has left the staging
@@ -434,7 +438,7 @@ typedef struct {
     int32_t block;        /* as tm_trace_opts */
     int32_t sort;
     int32_t max_steps;
-    int32_t reserved;
+    float eps;            /* the precision variant for every traced phase (0 = off) */
 } tm_server_opts;
 
 /* A finished request; times are host steady-clock nanoseconds. */

@@ -35,10 +35,10 @@ class _TraceOpts(C.Structure):
                 ("sort", C.c_int32), ("sort_chunk_log2", C.c_int32), ("sort_cells_log2", C.c_int32),
                 ("sort_dirq", C.c_int32), ("xcd_blocks", C.c_int32), ("eps", C.c_float), ("workspace", C.c_void_p), ("workspace_bytes", C.c_int64),
                 ("fp64_steps", C.c_void_p), ("order", C.c_void_p), ("queue_chunk", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("passes", C.c_int32)]
 
 _TRACE_KEYS = ("max_steps", "block", "kernel", "refill", "grid_cap", "xcds", "sort",
-               "sort_chunk_log2", "sort_cells_log2", "sort_dirq", "xcd_blocks", "queue_chunk")
+               "sort_chunk_log2", "sort_cells_log2", "sort_dirq", "xcd_blocks", "queue_chunk", "passes")
 
 
 def _trace_opts(kw, workspace=None, fp64_steps=None, n=0):
@@ -78,7 +78,7 @@ class _Request(C.Structure):
 class _ServerOpts(C.Structure):
     _fields_ = [("max_rays", C.c_int64), ("max_requests", C.c_int32), ("ring", C.c_int32),
                 ("block", C.c_int32), ("sort", C.c_int32), ("max_steps", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("eps", C.c_float)]
 
 
 class _Done(C.Structure):
@@ -391,9 +391,10 @@ def _request(mesh=0, kind="primary", width=64, height=64, eye=(0.5, 0.5, 0.5),
     return r
 
 
-def tm_server_create(handles, max_rays, max_requests=0, ring=0, block=0, sort=0, max_steps=0):
+def tm_server_create(handles, max_rays, max_requests=0, ring=0, block=0, sort=0, max_steps=0, eps=0.0):
     arr = (C.c_void_p * len(handles))(*handles)
-    o = _ServerOpts(int(max_rays), int(max_requests), int(ring), int(block), int(sort), int(max_steps), 0)
+    o = _ServerOpts(int(max_rays), int(max_requests), int(ring), int(block), int(sort), int(max_steps),
+                    float(eps))
     h = C.c_void_p()
     _check(_load().tm_server_create(arr, len(handles), C.byref(o), C.byref(h)))
     return h.value

@@ -158,7 +158,8 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
     const int64_t queue_bytes = queue ? queue_workspace_bytes() : 0;
     // the precision variant's two-pass form: a counter and a list of deferred rays
     // (without room for them it runs in one pass, with the same results)
-    int64_t defer_bytes = (o.eps > 0.0f && o.kernel != 2) ? 256 + sort_workspace_bytes(n_rays) : 0;
+    if (o.passes < 0 || o.passes > 2) return fail(TM_ERR_ARG, "%s: passes must be 0, 1 or 2", name);
+    int64_t defer_bytes = (o.eps > 0.0f && o.passes == 2) ? 256 + sort_workspace_bytes(n_rays) : 0;
     // where it goes: the given fixed workspace, the caller's, or the handle's own;
     // with none of them large enough an explicit sort = 2 or kernel = 3 is an
     // error and the automatic choice traces the rays unbinned
@@ -451,7 +452,7 @@ int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_prese
     if (rc != TM_OK) return rc;
     if (o.order) binned = false;
     *bytes = (binned ? tetrt::sort_workspace_bytes(n_rays) : 0) + (o.kernel == 3 ? tetrt::queue_workspace_bytes() : 0) +
-             ((o.eps > 0.0f && o.kernel != 2) ? 256 + tetrt::sort_workspace_bytes(n_rays) : 0);
+             ((o.eps > 0.0f && o.passes == 2) ? 256 + tetrt::sort_workspace_bytes(n_rays) : 0);
     return TM_OK;
 }
 

@@ -30,10 +30,12 @@ struct Shape {
     int32_t kernel = 1;   // 1 = one lane per ray, 3 = persistent waves on a queue
     int32_t qchunk = 0, refill = 0;   // kernel 3: rays per wave fetch, refill threshold
     int64_t qchunks = 0;  // kernel 3: chunks over all jobs
+    float eps = 0.0f;     // the precision variant (kernel 1)
     bool operator==(const Shape& o) const {
         return n_jobs == o.n_jobs && block == o.block && chunk_log2 == o.chunk_log2 && layout == o.layout &&
                xcds == o.xcds && blocks == o.blocks && chunks == o.chunks && steps == o.steps &&
-               kernel == o.kernel && qchunk == o.qchunk && refill == o.refill && qchunks == o.qchunks;
+               kernel == o.kernel && qchunk == o.qchunk && refill == o.refill && qchunks == o.qchunks &&
+               eps == o.eps;
     }
 };
 
@@ -94,7 +96,9 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
     if (o.queue_chunk < 0 || o.queue_chunk > 4096 || (o.queue_chunk & 63))
         return fail(TM_ERR_ARG, "tm_batch_set: queue_chunk must be a multiple of 64 in [64, 4096]");
     if (o.refill < 0 || o.refill > 64) return fail(TM_ERR_ARG, "tm_batch_set: refill must be in [0, 64]");
-    if (o.eps != 0.0f) return fail(TM_ERR_ARG, "tm_batch_set: the precision variant (eps > 0) is not batched");
+    if (!(o.eps >= 0.0f) || !(o.eps < 1.0f)) return fail(TM_ERR_ARG, "tm_batch_set: eps must be in [0, 1)");
+    if (o.eps > 0.0f && o.kernel == 3)
+        return fail(TM_ERR_ARG, "tm_batch_set: the precision variant (eps > 0) runs one lane per ray");
     if (o.sort < 0 || o.sort > 2) return fail(TM_ERR_ARG, "tm_batch_set: sort must be 0, 1 or 2");
     if (o.xcds < 0 || o.xcds > 64) return fail(TM_ERR_ARG, "tm_batch_set: xcds must be in [0, 64]");
     const int32_t block = o.block ? o.block : 256;
@@ -167,6 +171,7 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
     shape->qchunk = qchunk;
     shape->refill = o.refill ? o.refill : 16;
     shape->qchunks = qchunks;
+    shape->eps = o.eps;
     if (kernel == 3 && qchunks >= int64_t(0xFFFFFFFFu))
         return fail(TM_ERR_ARG, "tm_batch_set: too many queue chunks (raise queue_chunk)");
     // automatic: round-robin placement.  One contiguous range per XCD over a
@@ -217,7 +222,7 @@ hipError_t enqueue(const tm_batch_s* b, hipStream_t s) {
         return tetrt::launch_trace_batch_queue(b->d_table, sh.n_jobs, q, sh.layout, sh.steps, b->cus, s);
     }
     return tetrt::launch_trace_batch(b->d_table, sh.n_jobs, sh.blocks, sh.block, sh.layout, sh.xcds, sh.steps,
-                                     s);
+                                     sh.eps, s);
 }
 
 int check_batch(const tm_batch_s* b, const char* what) {
@@ -361,7 +366,7 @@ int tm_batch_tune(tm_batch b, int32_t reps, void* hip_stream, tm_trace_opts* cho
             if (cand >= 4 && o.xcds == 1) continue;   // a device with one XCD
             cands.push_back(o);
         }
-    for (int32_t ch : kChunks)
+    for (int32_t ch : (base.eps > 0.0f ? std::vector<int32_t>{} : std::vector<int32_t>(kChunks, kChunks + 4)))
         for (int32_t qc : kQChunks)
             for (int32_t rf : kRefills) {
                 tm_trace_opts o = base;

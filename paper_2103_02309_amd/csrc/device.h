@@ -113,8 +113,9 @@ struct Job {
 // share the record layout.  Rays without tmax get +inf.  xcds > 1: the blocks
 // are renumbered so that each XCD takes one contiguous range of them.  steps:
 // some job has a step-count array (the kernel then keeps per-ray counts).
+// eps > 0: the precision variant.
 hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_blocks, int32_t block,
-                              int32_t layout, int32_t xcds, bool steps, hipStream_t s);
+                              int32_t layout, int32_t xcds, bool steps, float eps, hipStream_t s);
 // The same walk by persistent waves draining the queue q over every job's rays
 // (zeroes q's counters first, with a kernel of its own); `cus` sizes the grid.
 hipError_t launch_trace_batch_queue(const Job* d_jobs, int32_t n_jobs, const Queue& q, int32_t layout,

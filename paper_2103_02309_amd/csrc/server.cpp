@@ -249,6 +249,7 @@ int step(tm_server_s* s, hipStream_t stream, int64_t* launched) {
     to.block = s->o.block;
     to.sort = s->o.sort;
     to.max_steps = s->o.max_steps;
+    to.eps = s->o.eps;
     int rc = tm_batch_set(sl.batch, int32_t(jobs.size()), jobs.data(), &to, stream);
     if (rc == TM_OK) rc = tm_batch_launch(sl.batch, stream);
     if (rc != TM_OK) return undo(rc);
@@ -336,6 +337,7 @@ int tm_server_create(const tm_mesh* meshes, int32_t n_meshes, const tm_server_op
         return fail(TM_ERR_ARG, "tm_server_create: block must be 64, 128 or 256");
     if (o.sort < 0 || o.sort > 2 || o.max_steps < 0)
         return fail(TM_ERR_ARG, "tm_server_create: bad sort or max_steps");
+    if (!(o.eps >= 0.0f) || !(o.eps < 1.0f)) return fail(TM_ERR_ARG, "tm_server_create: eps must be in [0, 1)");
     int dev = 0;
     (void)hipGetDevice(&dev);
     for (int32_t k = 0; k < n_meshes; ++k) {

@@ -447,13 +447,18 @@ __device__ __forceinline__ void walk_step_rec(const Mem& M, const Frame& f, cons
     }
     uint64_t S1 = N0 & P2, S2 = N1 & ~N0;
     if (PREC) {
-        int e = lane(S1) ? 1 : (lane(S2) ? 2 : 0);
-        if (unsure) {
-            e = exit_slot64(M, f, pc, w.a0, w.a1, w.a2, P);
-            ++pc.n64;
+        // the unsure lanes' decisions are replaced by the float64 ones; a wave with
+        // no unsure lane (nearly every step) skips all of it on one scalar branch
+        const uint64_t U = lanes(unsure);
+        if (U) {
+            int e = 0;
+            if (unsure) {
+                e = exit_slot64(M, f, pc, w.a0, w.a1, w.a2, P);
+                ++pc.n64;
+            }
+            S1 = (S1 & ~U) | lanes(unsure && e == 1);
+            S2 = (S2 & ~U) | lanes(unsure && e == 2);
         }
-        S1 = lanes(e == 1);
-        S2 = lanes(e == 2);
     }
     const bool s1 = lane(S1), s2 = lane(S2), s0 = lane(~(S1 | S2));
     const int32_t x = s1 ? w.a1 : (s2 ? w.a2 : w.a0);
@@ -1236,9 +1241,11 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
 // Batched launch: block b belongs to the job whose block range holds it (a
 // binary search that every lane of the block takes alike, so the job's
 // descriptors are read with scalar loads); the rest is the walk of k_trace.
-template <int LAYOUT, bool STEPS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
-k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs, uint32_t xcds) {
+// PREC: the precision variant with eps (every lane stays to the end, for the
+// ties its wave resolves together).
+template <int LAYOUT, bool STEPS, bool PREC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 4 : 8)))
+k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs, uint32_t xcds, float eps) {
     const int64_t b = xcd_block(blockIdx.x, gridDim.x, xcds, 0u);
     int lo = 0, hi = n_jobs;
     while (hi - lo > 1) {
@@ -1248,10 +1255,18 @@ k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs, uint32_t xcds) {
     const DevMesh m = jobs[lo].m;
     const RayArgs r = jobs[lo].r;
     const int64_t j = (b - jobs[lo].block0) * blockDim.x + threadIdx.x;
+    const Mem M = make_mem<LAYOUT>(m);
+    if (PREC) {
+        const int64_t i = j < r.n ? (r.perm ? int64_t(r.perm[j]) : j) : -1;
+        const bool valid = j < r.n && uint64_t(i) < uint64_t(r.n);
+        int32_t steps = 0, n64 = 0;
+        const bool tie = valid && trace_prec<true, LAYOUT, false>(m, M, r, i, eps, steps, n64, nullptr);
+        resolve_ties<true>(m, M, r, tie, i, steps, n64);
+        return;
+    }
     if (j >= r.n) return;
     const int64_t i = r.perm ? int64_t(r.perm[j]) : j;
     if (uint64_t(i) >= uint64_t(r.n)) return;
-    const Mem M = make_mem<LAYOUT>(m);
     Ray s;
     if (!setup_ray<true, LAYOUT, false>(m, M, r, i, s, 0.0f)) return;
     walk_ray<true, LAYOUT, STEPS>(M, s, r.max_steps);
@@ -1556,23 +1571,25 @@ hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, 
 }
 
 template <int LAYOUT>
-void launch_trace_batch_t(const Job* d_jobs, int32_t n_jobs, dim3 g, dim3 b, uint32_t X, bool steps,
+void launch_trace_batch_t(const Job* d_jobs, int32_t n_jobs, dim3 g, dim3 b, uint32_t X, bool steps, float eps,
                           hipStream_t s) {
-    if (steps)
-        hipLaunchKernelGGL((k_trace_batch<LAYOUT, true>), g, b, 0, s, d_jobs, n_jobs, X);
+    if (eps > 0.0f)
+        hipLaunchKernelGGL((k_trace_batch<LAYOUT, true, true>), g, b, 0, s, d_jobs, n_jobs, X, eps);
+    else if (steps)
+        hipLaunchKernelGGL((k_trace_batch<LAYOUT, true, false>), g, b, 0, s, d_jobs, n_jobs, X, 0.0f);
     else
-        hipLaunchKernelGGL((k_trace_batch<LAYOUT, false>), g, b, 0, s, d_jobs, n_jobs, X);
+        hipLaunchKernelGGL((k_trace_batch<LAYOUT, false, false>), g, b, 0, s, d_jobs, n_jobs, X, 0.0f);
 }
 
 hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_blocks, int32_t block,
-                              int32_t layout, int32_t xcds, bool steps, hipStream_t s) {
+                              int32_t layout, int32_t xcds, bool steps, float eps, hipStream_t s) {
     const uint32_t X = uint32_t(std::max(1, xcds));
     if (total_blocks <= 0 || n_jobs <= 0) return hipSuccess;
     const dim3 g{unsigned(total_blocks)}, b{unsigned(block)};
-    if (layout == kTet16) launch_trace_batch_t<kTet16>(d_jobs, n_jobs, g, b, X, steps, s);
-    else if (layout == kTet32N) launch_trace_batch_t<kTet32N>(d_jobs, n_jobs, g, b, X, steps, s);
-    else if (layout == kTet32) launch_trace_batch_t<kTet32>(d_jobs, n_jobs, g, b, X, steps, s);
-    else launch_trace_batch_t<kTet20>(d_jobs, n_jobs, g, b, X, steps, s);
+    if (layout == kTet16) launch_trace_batch_t<kTet16>(d_jobs, n_jobs, g, b, X, steps, eps, s);
+    else if (layout == kTet32N) launch_trace_batch_t<kTet32N>(d_jobs, n_jobs, g, b, X, steps, eps, s);
+    else if (layout == kTet32) launch_trace_batch_t<kTet32>(d_jobs, n_jobs, g, b, X, steps, eps, s);
+    else launch_trace_batch_t<kTet20>(d_jobs, n_jobs, g, b, X, steps, eps, s);
     return hipGetLastError();
 }
 

@@ -120,6 +120,22 @@ def test_batch_matches_single(tetrt, scenes, uploaded, kw):
     b.free()
 
 
+@pytest.mark.parametrize("eps", [1e-6, 1e-4])
+def test_batch_precision_matches_single(tetrt, scenes, uploaded, eps):
+    """The precision variant in a batch gives each job what trace_closest with the
+    same eps gives it, bit for bit (and the oracle's ids, as test_batch_oracle)."""
+    jobs = _jobs(tetrt, scenes, uploaded)
+    b = tetrt.Batch(max_jobs=len(jobs), max_rays=sum(int(j["orig"].shape[0]) for j in jobs))
+    b.set(jobs, eps=eps)
+    _fill(jobs)
+    b.launch()
+    for k, j in enumerate(jobs):
+        res = j["mesh"].trace(j["orig"], j["dirs"], tmax=j.get("tmax"), start_face=j.get("start_face"),
+                              want_tets=True, want_steps=True, eps=eps)
+        _same(_host(j["out"]), _host(res), "job %d" % k)
+    b.free()
+
+
 def test_batch_without_step_counts(tetrt, scenes, uploaded):
     """Jobs without step-count or tet-id outputs take the batch kernel that keeps
     no per-ray counts; results equal the counting path bit for bit."""
@@ -224,7 +240,7 @@ def test_batch_errors(tetrt, scenes, uploaded):
     with pytest.raises(tetrt.TetRTError, match="layout"):
         b.set(mixed)
     with pytest.raises(tetrt.TetRTError, match="precision"):
-        b.set(jobs, eps=1e-6)
+        b.set(jobs, eps=1e-6, kernel=3)
     with pytest.raises(tetrt.TetRTError, match="one lane per ray"):
         b.set(jobs, kernel=2)
     with pytest.raises(tetrt.TetRTError, match="queue_chunk"):

@@ -100,7 +100,7 @@ def test_precision_sweep(stress, eps):
 @pytest.mark.parametrize("eps", [1e-6, 1e-4])
 def test_two_pass_equals_one_pass(stress, eps):
     """The two-pass form (a float32 walk that defers its unsure rays to a list, then
-    the float64-capable kernel on the list; taken when a workspace is at hand) gives
+    the float64-capable kernel on the list; passes = 2 with a workspace) gives
     the one-pass precision variant's results bit for bit, also in bin order."""
     import paper_2103_02309_amd as tetrt
     m, om, mesh, o, d, kind, ref = stress
@@ -109,7 +109,7 @@ def test_two_pass_equals_one_pass(stress, eps):
     tm = torch.from_numpy(np.random.default_rng(3).uniform(0.1, 2.0, n).astype(np.float32)).cuda()
     for tmax in (None, tm):
         two = mesh.trace(O, D, tmax=tmax, want_steps=True, want_tets=True, want_fp64=True, eps=eps,
-                         max_steps=20000)
+                         max_steps=20000, passes=2)
         one = tetrt.outputs(n, "cuda:0", want_tets=True, want_steps=True)
         one["fp64_steps"] = torch.empty(n, dtype=torch.int32, device="cuda:0")
         tetrt.binding.trace_closest(mesh.handle, O, D, one["tri"], one["t"], one["bary"], tmax=tmax,
@@ -120,7 +120,7 @@ def test_two_pass_equals_one_pass(stress, eps):
             a, b = two[k].cpu().numpy(), one[k].cpu().numpy()
             assert np.array_equal(a, b, equal_nan=True), (eps, tmax is None, k, int((a != b).sum()))
         binned = mesh.trace(O, D, tmax=tmax, want_steps=True, want_tets=True, want_fp64=True, eps=eps,
-                            max_steps=20000, sort=2)
+                            max_steps=20000, sort=2, passes=2)
         torch.cuda.synchronize()
         for k in two:
             assert np.array_equal(binned[k].cpu().numpy(), two[k].cpu().numpy(), equal_nan=True), ("binned", k)

@@ -62,14 +62,14 @@ def _rays(tetrt, mesh, req, phase, prev=None):
     return {"orig": o, "dirs": d, "tmax": tm, "sf": sf}
 
 
-def _reference(tetrt, mesh, req):
+def _reference(tetrt, mesh, req, **kw):
     """trace_closest on the request's own rays, phase by phase."""
     r0 = _rays(tetrt, mesh, req, 0)
-    res0 = mesh.trace(r0["orig"], r0["dirs"], tmax=r0["tmax"], start_face=r0["sf"])
+    res0 = mesh.trace(r0["orig"], r0["dirs"], tmax=r0["tmax"], start_face=r0["sf"], **kw)
     if req["kind"] == "primary":
         return _host(res0)
     r1 = _rays(tetrt, mesh, req, 1, dict(r0, tri=res0["tri"], t=res0["t"]))
-    return _host(mesh.trace(r1["orig"], r1["dirs"], tmax=r1["tmax"], start_face=r1["sf"]))
+    return _host(mesh.trace(r1["orig"], r1["dirs"], tmax=r1["tmax"], start_face=r1["sf"], **kw))
 
 
 def test_camera_rays_match_pinhole_definition(tetrt, scene):
@@ -140,6 +140,21 @@ def test_server_equals_trace(tetrt, scene, kind):
     assert done[0]["submit_ns"] <= done[0]["admit_ns"] <= done[0]["done_ns"]
     assert done[0]["rays"] == 96 * 64 * (1 if kind == "primary" else 2)
     _same(_host(out), _reference(tetrt, meshes[k], req), kind)
+    srv.free()
+
+
+@pytest.mark.parametrize("kind", ["primary", "ao"])
+def test_server_precision_equals_trace(tetrt, scene, kind):
+    """A server created with eps serves what trace_closest with that eps gives."""
+    specs, hosts, meshes = scene
+    k = 3
+    req = _req(specs[k], k, kind, 64, 64)
+    out = tetrt.outputs(64 * 64, "cuda:0")
+    srv = tetrt.Server(meshes, max_rays=1 << 16, eps=1e-6)
+    srv.submit(out, **req)
+    srv.drain()
+    assert len(srv.poll()) == 1
+    _same(_host(out), _reference(tetrt, meshes[k], req, eps=1e-6), kind)
     srv.free()
 
 
