@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--kernel", type=int, default=0,
                     help="0 auto, 1 one lane per ray, 2 persistent lanes, 3 persistent waves on a work queue")
     ap.add_argument("--refill", type=int, default=0, help="persistent refill threshold (0 = default)")
+    ap.add_argument("--queue-chunk", type=int, default=0,
+                    help="kernel 3: rays a wave takes from the queue at a time (0 = default)")
     ap.add_argument("--ao", type=int, default=8, help="AO rays per primary hit")
     ap.add_argument("--sort", type=int, default=0, help="ray binning: 0 auto, 1 off, 2 on")
     ap.add_argument("--sort-chunk", type=int, default=0, help="log2 rays per binning chunk (0 = default)")
@@ -204,7 +206,8 @@ def main():
 
     # binning: the library's automatic rule (batches of at least 2^18 rays that carry
     # tmax), run as its own kernel so that the walk kernel is timed apart
-    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill, eps=args.eps, passes=args.passes)
+    kw = dict(block=args.block, kernel=args.kernel, refill=args.refill, eps=args.eps, passes=args.passes,
+              queue_chunk=args.queue_chunk)
     skw = dict(sort_chunk_log2=args.sort_chunk, sort_dirq=args.sort_dirq, sort_cells_log2=args.sort_cells)
     bin_p = args.sort == 2
     bin_a = args.sort == 2 or (args.sort == 0 and n_a >= (1 << 18))
@@ -262,17 +265,17 @@ def main():
     achieved = dom_ops / (dom_ms * 1e-3) / 1e12
     alg_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
     traffic, l1_acc, l2_req, l2_hit = measured_counters(args) if dom == "ao" else (None,) * 4
-    l1_peak, fill_peak = l1_rates()
+    calib = l1_calibration()
     mem = None
-    if l1_acc and l2_req and l1_peak:
+    if l1_acc and l2_req and calib:
         cyc = dom_ms * 1e-3 * CLOCK_HZ * N_CUS   # CU-cycles of one launch
-        # the L1 serves a hit in 1/l1_peak and a fill in 1/fill_peak of a CU-cycle
-        # (calibrated): its busy fraction is the sum over the launch's hits and fills
-        busy = ((l1_acc - l2_req) / l1_peak + l2_req / fill_peak) / cyc
-        mem = {"l1_lookups_per_cu_cycle": round(l1_acc / cyc, 3), "l1_lookup_peak": l1_peak,
-               "l1_frac": round(l1_acc / cyc / l1_peak, 4),
-               "l2_fills_per_cu_cycle": round(l2_req / cyc, 3), "l2_fill_peak": fill_peak,
-               "l2_fill_frac": round(l2_req / cyc / fill_peak, 4), "l1_busy_frac": round(busy, 4)}
+        miss = l2_req / l1_acc
+        peak = l1_peak_at(calib, miss)
+        mem = {"l1_lookups_per_cu_cycle": round(l1_acc / cyc, 4), "l1_miss_rate": round(miss, 4),
+               "l1_lookup_peak_at_miss_rate": round(peak, 4) if peak else None,
+               "l1_frac": round(l1_acc / cyc / peak, 4) if peak else None,
+               "l2_fills_per_cu_cycle": round(l2_req / cyc, 4),
+               "calibration": [{"miss_rate": m_, "lookups_per_cu_cycle": r_} for m_, r_ in calib]}
     hbm_gbs = traffic / (dom_ms * 1e-3) / 1e9 if traffic else None
 
     line = {
@@ -307,17 +310,20 @@ def main():
         },
         "roofline": {
             # The dominant kernel (the AO walk) reads far fewer bytes from HBM than
-            # the method names (20 B per step + ray I/O): the 227 MB hot set sits in
-            # the last-level cache and L2 hits 96%.  What binds it is the L1: its hits
-            # and its fills from L2 together keep it busy about every cycle
-            # (calibrated per-CU rates, memory_pipeline).  So "bound" names the L1
-            # and "frac" is its busy fraction; HBM is reported from measured bytes
-            # ("hbm", "traffic"), and the method's algorithmic byte rate apart
-            # ("algorithmic"), never as an HBM fraction.
-            "bound": "l1" if mem else None,
-            "achieved": mem["l1_busy_frac"] if mem else None,
-            "peak": 1.0, "unit": "L1 busy fraction (hits + fills at calibrated rates)",
-            "frac": mem["l1_busy_frac"] if mem else None,
+            # the method names (20 B per walk step + ray I/O): its 227 MB hot set sits
+            # in the last-level cache and L2 hits 96%.  What binds it is the L1: a
+            # wave load whose lanes read distinct lines costs one lookup per line, and
+            # the L1 serves lookups at a rate that falls as the share of misses (fills
+            # from L2) rises.  So "bound" names the L1, "achieved" is the walk's L1
+            # lookups per CU-cycle and "peak" the rate the calibration kernel attains
+            # at the same miss rate; HBM is reported from measured bytes ("hbm",
+            # "traffic"), the method's algorithmic byte rate apart ("algorithmic"),
+            # never as an HBM fraction.
+            "bound": "l1" if mem and mem["l1_frac"] else None,
+            "achieved": mem["l1_lookups_per_cu_cycle"] if mem and mem["l1_frac"] else None,
+            "peak": mem["l1_lookup_peak_at_miss_rate"] if mem else None,
+            "unit": "L1 lookups per CU per cycle",
+            "frac": mem["l1_frac"] if mem else None,
             "traffic": traffic,
             "kernel": "k_trace (%s rays)" % dom, "kernel_ms": round(float(dom_ms), 4),
             "hbm": {"achieved": round(hbm_gbs, 1) if hbm_gbs else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -428,16 +434,27 @@ def attainable_copy_gbs(torch, dev, nbytes=1 << 30, reps=5):
     return round(2 * nbytes / (sorted(ms)[reps // 2] * 1e-3) / 1e9, 1)
 
 
-def l1_rates():
-    """The memory pipeline's per-CU rates for 16-byte lane loads, from the
-    committed calibration summary: L1 lookups per cycle (lanes on distinct lines
-    spread over the line's offsets, all hits) and L1 fills from L2 per cycle
-    (all misses); (None, None) if absent."""
-    vals = summary_values(L1_SUMMARY, ("l1_lookups_per_cu_cycle", "l2_fills_per_cu_cycle"))
+def l1_calibration():
+    """The calibration kernel's L1 lookup rate for random 16-byte lane loads
+    against its L1 miss rate, [(miss_rate, lookups per CU-cycle)] sorted by miss
+    rate, from the committed summary; None if absent."""
+    vals = summary_values(L1_SUMMARY, ("l1_calibration",))
     try:
-        return float(vals["l1_lookups_per_cu_cycle"]), float(vals["l2_fills_per_cu_cycle"])
+        pts = sorted((float(a), float(b)) for a, b in (x.split(":") for x in vals["l1_calibration"].split(",")))
     except (KeyError, ValueError):
-        return None, None
+        return None
+    return pts if len(pts) >= 2 else None
+
+
+def l1_peak_at(calib, miss):
+    """Lookup rate the calibration reaches at L1 miss rate ``miss``: cycles per
+    lookup interpolated linearly between the two calibrated miss rates around it
+    (None outside their range)."""
+    for (m0, r0), (m1, r1) in zip(calib, calib[1:]):
+        if m0 <= miss <= m1:
+            w = (miss - m0) / (m1 - m0) if m1 > m0 else 0.0
+            return 1.0 / ((1.0 - w) / r0 + w / r1)
+    return None
 
 
 def bench_precision(args, tetrt, dev, log):
@@ -556,6 +573,9 @@ def bench_l1probe(args, tetrt, dev, log):
              ("random", 1 << 20, 128, "random 128-B lines, 128 MiB set"),
              ("random", 256, 64, "random 64-B units, 16 KiB set"),
              ("random", 1 << 10, 16, "random 16-B units, 16 KiB set"),
+             ("random", 1 << 11, 16, "random 16-B units, 32 KiB set"),
+             ("random", 1 << 9, 80, "random 16-B reads in 80-B units, 40 KiB set"),
+             ("random", 1 << 10, 48, "random 16-B reads in 48-B units, 48 KiB set"),
              ("random", 1 << 12, 16, "random 16-B units, 64 KiB set"),
              ("random", 1 << 14, 16, "random 16-B units, 256 KiB set"),
              ("random", 1 << 17, 16, "random 16-B units, 2 MiB set"),
@@ -627,7 +647,7 @@ def bench_batch(args, tetrt, dev, log):
         del m
     rays = sum(int(j["orig"].shape[0]) for j in jobs)
     kw = dict(block=args.block, sort=args.sort, sort_chunk_log2=args.sort_chunk,
-              sort_dirq=args.sort_dirq, sort_cells_log2=args.sort_cells)
+              sort_dirq=args.sort_dirq, sort_cells_log2=args.sort_cells, eps=args.eps)
     sep_out = [tetrt.outputs(int(j["orig"].shape[0]), dev) for j in jobs]
 
     def separate():
@@ -652,10 +672,13 @@ def bench_batch(args, tetrt, dev, log):
     ms_sep = timed(separate, K)
     ms_batch = timed(b.launch, K)
     ms_graph = timed(b.graph_launch, K)
-    # persistent waves draining one queue over all jobs, with its defaults
-    b.set(jobs, kernel=3)
-    ms_queue = timed(b.launch, K)
-    ms_queue_graph = timed(b.graph_launch, K)
+    # persistent waves draining one queue over all jobs, with its defaults (float32
+    # walk only)
+    ms_queue = ms_queue_graph = None
+    if args.eps == 0.0:
+        b.set(jobs, kernel=3)
+        ms_queue = timed(b.launch, K)
+        ms_queue_graph = timed(b.graph_launch, K)
     b.set(jobs, **kw)
     chosen, _ = b.tune(reps=3)
     ms_tuned = timed(b.launch, K)
@@ -667,7 +690,9 @@ def bench_batch(args, tetrt, dev, log):
         for key in ("tri", "t", "bary"):
             x, y = j["out"][key], out[key]
             mism += int((~((x == y) | (torch.isnan(x) & torch.isnan(y)))).sum().item())
-    best = min(ms_batch, ms_graph, ms_queue, ms_queue_graph, ms_tuned, ms_tuned_graph)
+    best = min(x for x in (ms_batch, ms_graph, ms_queue, ms_queue_graph, ms_tuned, ms_tuned_graph)
+               if x is not None)
+    r4 = lambda x: None if x is None else round(x, 4)
     line = {
         "metric": "batched closest-hit Mrays/s over %d meshes" % len(jobs),
         "value": round(rays / (best * 1e-3) / 1e6, 2),
@@ -676,10 +701,11 @@ def bench_batch(args, tetrt, dev, log):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "%d Kuhn meshes n log-uniform 8..96, 1-10 spheres, 1K-1M rays each "
                                "(half primary, half AO)" % len(jobs),
-                   "tets": total_tets, "rays": rays, "layout": args.layout, "tuned": chosen},
+                   "tets": total_tets, "rays": rays, "layout": args.layout, "precision_eps": args.eps,
+                   "tuned": chosen},
         "detail": {"separate_launches_ms": round(ms_sep, 4), "batch_ms": round(ms_batch, 4),
-                   "batch_graph_ms": round(ms_graph, 4), "queue_ms": round(ms_queue, 4),
-                   "queue_graph_ms": round(ms_queue_graph, 4), "tuned_ms": round(ms_tuned, 4),
+                   "batch_graph_ms": round(ms_graph, 4), "queue_ms": r4(ms_queue),
+                   "queue_graph_ms": r4(ms_queue_graph), "tuned_ms": round(ms_tuned, 4),
                    "tuned_graph_ms": round(ms_tuned_graph, 4),
                    "separate_mrays_s": round(rays / (ms_sep * 1e-3) / 1e6, 2),
                    "batch_vs_separate": round(ms_sep / best, 3),

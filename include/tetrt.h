@@ -126,7 +126,7 @@ typedef struct {
                             the others'), stages their ids in LDS and refills its finished
                             lanes from them (needs a workspace, as binning does) */
     int32_t refill;      /* kernels 2 and 3: finished lanes per wavefront that trigger a
-                            refill, 1..64 (0 = 16) */
+                            refill, 1..64 (0 = 16 for kernel 2, 64 for kernel 3) */
     int32_t grid_cap;    /* persistent lanes: at most this many blocks (0 = enough blocks
                             to fill every compute unit) */
     int32_t xcds;        /* one lane per ray: number of accelerator dies (XCDs, 8 on MI355X)
@@ -167,7 +167,7 @@ typedef struct {
                             tetmesh_bin_rays; entries out of range are skipped).  Replaces
                             the call's own binning (sort is then ignored) */
     int32_t queue_chunk; /* kernel 3: rays a wave takes from the queue at a time, a multiple
-                            of 64 in [64, 4096] (0 = 256) */
+                            of 64 in [64, 4096] (0 = 64) */
     int32_t passes;      /* precision variant: 0 or 1 = one pass; 2 = two passes, a float32
                             walk that defers the rays meeting an unsure step to a list, then
                             the float64-capable walk of the listed rays only (same results;
@@ -372,7 +372,7 @@ int tm_batch_graph_launch(tm_batch b, void* hip_stream);
  * 2^13 rays per chunk) and die placement (round-robin; one contiguous range of
  * blocks per XCD) of the one-lane-per-ray kernel, and for the queue kernel
  * each binning setting, rays per wave fetch (queue_chunk 64, 256, 1024) and
- * refill threshold (8, 32), reps timed launches each after one warm-up, with
+ * refill threshold (16, 64), reps timed launches each after one warm-up, with
  * HIP events on hip_stream, and keeps the fastest.  Overwrites the jobs' outputs
  * (with the same results).  Synchronous.  chosen host, nullable: receives the
  * options kept; ms host, nullable: their mean launch time in milliseconds.

@@ -219,7 +219,10 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
     c.block = o.block ? o.block : ((binned || o.order) ? 256 : 128);
     c.cus = m->cus;
     c.waves_per_simd = 8;
-    c.refill = o.refill ? o.refill : 16;
+    // persistent lanes refill at 16 finished lanes; the queue kernel's waves only once
+    // all their lanes are done (refilling idle lanes earlier cost more than it saved:
+    // main workload, primary 1.64 against 1.11 ms, AO 5.71 against 2.29 ms)
+    c.refill = o.refill ? o.refill : (o.kernel == 3 ? 64 : 16);
     c.grid_cap = o.grid_cap;
     // automatic: binned launches (their rays are ordered along the image, then by
     // direction inside each chunk) give each XCD one contiguous range of blocks, so
@@ -234,7 +237,9 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
     if (queue) {
         char* base = static_cast<char*>(ws) + perm_bytes;
         c.queue.cursor = reinterpret_cast<uint32_t*>(base);
-        c.queue.chunk = uint32_t(o.queue_chunk ? o.queue_chunk : 256);
+        // 64 rays per fetch (one per lane) balances the waves' loads best (main
+        // workload, refill 64: primary 1.11 against 2.00 ms with 256, AO 2.29 against 2.86)
+        c.queue.chunk = uint32_t(o.queue_chunk ? o.queue_chunk : 64);
         c.queue.n_chunks = uint32_t((n_rays + c.queue.chunk - 1) / c.queue.chunk);
         c.queue.xcds = uint32_t(o.xcds ? o.xcds : xcd_count(m->cus));
         c.queue.refill = c.refill;

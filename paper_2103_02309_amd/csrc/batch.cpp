@@ -105,7 +105,7 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
     const int32_t chunk_log2 = o.sort_chunk_log2 ? o.sort_chunk_log2 : 12;
     table->assign(size_t(n_jobs), tetrt::Job{});
     const int32_t kernel = o.kernel == 3 ? 3 : 1;
-    const int32_t qchunk = o.queue_chunk ? o.queue_chunk : 256;
+    const int32_t qchunk = o.queue_chunk ? o.queue_chunk : 64;
     int64_t blocks = 0, chunks = 0, rays = 0, perm_at = 0, qchunks = 0;
     int32_t layout = -1;
     for (int32_t k = 0; k < n_jobs; ++k) {
@@ -169,7 +169,7 @@ int build_table(tm_batch_s* b, int32_t n_jobs, const tm_job* jobs, const tm_trac
     shape->chunks = chunks;
     shape->kernel = kernel;
     shape->qchunk = qchunk;
-    shape->refill = o.refill ? o.refill : 16;
+    shape->refill = o.refill ? o.refill : (kernel == 3 ? 64 : 16);
     shape->qchunks = qchunks;
     shape->eps = o.eps;
     if (kernel == 3 && qchunks >= int64_t(0xFFFFFFFFu))
@@ -349,7 +349,7 @@ int tm_batch_tune(tm_batch b, int32_t reps, void* hip_stream, tm_trace_opts* cho
     static const int32_t kBlocks[3] = {64, 128, 256};
     static const int32_t kChunks[4] = {0, 11, 12, 13};  // 0 = no binning
     static const int32_t kQChunks[3] = {64, 256, 1024};
-    static const int32_t kRefills[2] = {8, 32};
+    static const int32_t kRefills[2] = {16, 64};
     const int32_t xcd_opts[2] = {1, tetrt::xcd_count(b->cus)};
     // candidates: the one-lane-per-ray kernel over block size x binning x placement,
     // then the queue kernel over binning x rays per fetch x refill threshold

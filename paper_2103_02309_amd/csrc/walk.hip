@@ -924,7 +924,7 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
 // One lane per ray: set-up, walk, result.
 // 8 waves per SIMD (at most 64 VGPRs): the walk is latency-bound, so occupancy
 // is what hides the memory round trips.  The precision variant carries float64
-// code; it runs 7 waves (without tmax) or 4 (with): at these register budgets
+// code; it runs 7 waves (without tmax) or 5 (with): at these register budgets
 // its step loop keeps every value in registers, and the spilled values are
 // those of the rare float64 paths and of set-up.
 // The dispatcher deals blocks to the XCDs round-robin (block b runs on XCD
@@ -1127,7 +1127,7 @@ __device__ __forceinline__ bool trace_prec(const DevMesh& m, const Mem& M, const
 }
 
 template <bool TMAX, int LAYOUT, bool PREC, bool STEPS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? (TMAX ? 4 : 7) : 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? (TMAX ? 5 : 7) : 8)))
 k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds, kn.xcd_blocks)) * blockDim.x + threadIdx.x;
     const Mem M = make_mem<LAYOUT>(m);
@@ -1244,7 +1244,7 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
 // PREC: the precision variant with eps (every lane stays to the end, for the
 // ties its wave resolves together).
 template <int LAYOUT, bool STEPS, bool PREC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 4 : 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 5 : 8)))
 k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs, uint32_t xcds, float eps) {
     const int64_t b = xcd_block(blockIdx.x, gridDim.x, xcds, 0u);
     int lo = 0, hi = n_jobs;
