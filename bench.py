@@ -461,37 +461,30 @@ def bench_precision(args, tetrt, dev, log):
     """The precision variant on the stress set: 2,000,000 rays on the 16^3 scene
     (10% aimed through mesh vertices, 10% along non-surface edges, 80% random),
     for eps = 0 (plain float32 walk) and the sweep 1e-7 .. 1e-4: walk time and
-    Mrays/s (every ray locates its own origin), and per ray kind the share of rays
-    whose triangle differs from the FP64 oracle's, how many of those are not
-    explained by an edge/vertex tie, step caps and invalid results, and the share
-    of steps decided in float64."""
+    Mrays/s (every ray locates its own origin), step caps, invalid results and
+    the share of steps decided in float64.  Its CPU-baseline leg (on unless
+    --cpu-baseline 0) runs the FP64 oracle on the same rays, reports its rate, and
+    per ray kind the share of rays whose triangle differs from the oracle's, how
+    many of those are not explained by an edge/vertex tie, and the largest t and
+    barycentric errors of the matched hits."""
     import numpy as np
     import torch
-    import oracle
-    from oracle.compare import compare
     from synth import config_mesh, precision_rays
     m = config_mesh("tiny")
-    om = oracle.OracleMesh.from_kuhn(m)
     n = 2_000_000
     o, d, kind = precision_rays(m.points, m.tets, m.cflag, n=n, seed=4)
-    t0 = time.time()
-    threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
-    from concurrent.futures import ThreadPoolExecutor
-    b = np.linspace(0, n, threads + 1).astype(np.int64)
-    with ThreadPoolExecutor(threads) as ex:
-        parts = list(ex.map(lambda k: om.trace(o[b[k]:b[k + 1]], d[b[k]:b[k + 1]]), range(threads)))
-    ref = {key: np.concatenate([p[key] for p in parts]) for key in parts[0]}
-    log("oracle: %d rays in %.1f s on %d threads" % (n, time.time() - t0, threads))
+    kinds = {0: "random", 1: "through vertices", 2: "along edges"}
     mesh = tetrt.upload(m.points, m.tets, m.nbrs, m.cflag, layout=args.layout)
     O, D = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
     out = tetrt.outputs(n, dev, want_steps=True)
     out["fp64_steps"] = torch.empty(n, dtype=torch.int32, device=dev)
-    rows = []
+    rows, results = [], {}
     for eps in (0.0, 1e-7, 1e-6, 1e-5, 1e-4):
         kw = dict(eps=eps, max_steps=20000)
-        mesh.trace_into(out, O, D, **kw)   # warm-up, and the results checked below
+        mesh.trace_into(out, O, D, **kw)   # warm-up, and the results reported below
         torch.cuda.synchronize()
         got = {k: v.cpu().numpy() for k, v in out.items()}
+        results[eps] = got
         ms = []
         for _ in range(max(3, args.steps // 4)):
             a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -503,22 +496,56 @@ def bench_precision(args, tetrt, dev, log):
         t = sorted(ms)[len(ms) // 2]
         row = {"eps": eps, "ms": round(t, 4), "mrays_s": round(n / t / 1e3, 1),
                "fp64_step_share": round(float(got["fp64_steps"].sum()) / max(1.0, float(got["steps"].clip(0).sum())), 6)}
-        for k, name in {0: "random", 1: "through vertices", 2: "along edges"}.items():
+        for k, name in kinds.items():
             sel = kind == k
-            rep = compare(m.points, om.tri_verts, o[sel], d[sel], {x: v[sel] for x, v in ref.items()},
-                          {x: v[sel] for x, v in got.items()})
-            row[name] = {"rays": int(sel.sum()), "mismatch_rate": round(1.0 - rep["frac_identical"], 7),
-                         "unexplained": int(rep["n_unexplained"]),
-                         "step_caps": int((got["tri"][sel] == -2).sum()),
+            row[name] = {"rays": int(sel.sum()), "step_caps": int((got["tri"][sel] == -2).sum()),
                          "invalid": int((got["tri"][sel] == -3).sum())}
         rows.append(row)
         log(json.dumps(row))
     mesh.free()
+    base = None
+    if args.cpu_baseline:
+        base = precision_cpu_baseline(args, m, o, d, kind, kinds, results, rows, log)
     print(json.dumps({"metric": "precision variant on 2M stress rays (16^3 scene)", "unit": "Mrays/s",
                       "dtype": "f32 walk, f64 re-evaluation", "data": "synthetic", "rows": rows,
                       "config": {"workload": "kuhn16-sphere, 2M rays: 10% through vertices, 10% along "
-                                             "non-surface edges, 80% random", "layout": args.layout}}),
-          flush=True)
+                                             "non-surface edges, 80% random", "layout": args.layout},
+                      "cpu_baseline": base}), flush=True)
+
+
+def precision_cpu_baseline(args, m, o, d, kind, kinds, results, rows, log):
+    """The precision workload's CPU-baseline leg: the FP64 oracle on all its rays
+    (threads over contiguous ranges), its rate, and the GPU results of every eps
+    compared with it (the parity rule of oracle/compare.py), added to ``rows``."""
+    import numpy as np
+    import oracle
+    from oracle.compare import compare
+    from concurrent.futures import ThreadPoolExecutor
+    om = oracle.OracleMesh.from_kuhn(m)
+    n = o.shape[0]
+    threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+    b = np.linspace(0, n, threads + 1).astype(np.int64)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda k: om.trace(o[b[k]:b[k + 1]], d[b[k]:b[k + 1]]), range(threads)))
+    wall = time.perf_counter() - t0
+    ref = {key: np.concatenate([p[key] for p in parts]) for key in parts[0]}
+    log("oracle: %d rays in %.1f s on %d threads" % (n, wall, threads))
+    for row in rows:
+        got = results[row["eps"]]
+        ident = 0
+        for k, name in kinds.items():
+            sel = kind == k
+            rep = compare(m.points, om.tri_verts, o[sel], d[sel], {x: v[sel] for x, v in ref.items()},
+                          {x: v[sel] for x, v in got.items()})
+            ident += rep["identical"]
+            row[name].update({"mismatch_rate": round(1.0 - rep["frac_identical"], 7),
+                              "unexplained": int(rep["n_unexplained"]),
+                              "max_t_rel": float("%.3g" % rep["max_t_rel"]),
+                              "max_bary": float("%.3g" % rep["max_bary"])})
+        row["identical_all"] = round(ident / n, 6)
+    return {"value": round(n / wall / 1e6, 4), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": "all %d rays, %.1f s wall on %d threads" % (n, wall, threads)}
 
 
 _PROBE_MODES = {"random": 0, "8_lanes": 1, "one_line": 2}
