@@ -270,12 +270,19 @@ def main():
     if l1_acc and l2_req and calib:
         cyc = dom_ms * 1e-3 * CLOCK_HZ * N_CUS   # CU-cycles of one launch
         miss = l2_req / l1_acc
-        peak = l1_peak_at(calib, miss)
+        # the calibration's rate at this miss rate, for independent loads and for
+        # chained ones (each address from the previous load, as in a walk); the
+        # peak is the higher of the two
+        ind = l1_peak_at(calib, miss)
+        dep_cal = l1_calibration("l1_calibration_dependent")
+        dep = l1_peak_at(dep_cal, miss) if dep_cal else None
+        peak = max([x for x in (ind, dep) if x], default=None)
         mem = {"l1_lookups_per_cu_cycle": round(l1_acc / cyc, 4), "l1_miss_rate": round(miss, 4),
                "l1_lookup_peak_at_miss_rate": round(peak, 4) if peak else None,
                "l1_frac": round(l1_acc / cyc / peak, 4) if peak else None,
-               "l2_fills_per_cu_cycle": round(l2_req / cyc, 4),
-               "calibration": [{"miss_rate": m_, "lookups_per_cu_cycle": r_} for m_, r_ in calib]}
+               "l1_lookup_rate_independent_at_miss_rate": round(ind, 4) if ind else None,
+               "l1_lookup_rate_dependent_at_miss_rate": round(dep, 4) if dep else None,
+               "l2_fills_per_cu_cycle": round(l2_req / cyc, 4)}
     hbm_gbs = traffic / (dom_ms * 1e-3) / 1e9 if traffic else None
 
     line = {
@@ -315,8 +322,8 @@ def main():
             # wave load whose lanes read distinct lines costs one lookup per line, and
             # the L1 serves lookups at a rate that falls as the share of misses (fills
             # from L2) rises.  So "bound" names the L1, "achieved" is the walk's L1
-            # lookups per CU-cycle and "peak" the rate the calibration kernel attains
-            # at the same miss rate; HBM is reported from measured bytes ("hbm",
+            # lookups per CU-cycle and "peak" the highest rate the calibration kernel
+            # attains at the same miss rate; HBM is reported from measured bytes ("hbm",
             # "traffic"), the method's algorithmic byte rate apart ("algorithmic"),
             # never as an HBM fraction.
             "bound": "l1" if mem and mem["l1_frac"] else None,
@@ -434,13 +441,15 @@ def attainable_copy_gbs(torch, dev, nbytes=1 << 30, reps=5):
     return round(2 * nbytes / (sorted(ms)[reps // 2] * 1e-3) / 1e9, 1)
 
 
-def l1_calibration():
+def l1_calibration(key="l1_calibration"):
     """The calibration kernel's L1 lookup rate for random 16-byte lane loads
     against its L1 miss rate, [(miss_rate, lookups per CU-cycle)] sorted by miss
-    rate, from the committed summary; None if absent."""
-    vals = summary_values(L1_SUMMARY, ("l1_calibration",))
+    rate, from the committed summary; None if absent.  ``l1_calibration``:
+    independent loads (the L1's throughput); ``l1_calibration_dependent``: each
+    lane's loads a chain, each address depending on the previous load."""
+    vals = summary_values(L1_SUMMARY, (key,))
     try:
-        pts = sorted((float(a), float(b)) for a, b in (x.split(":") for x in vals["l1_calibration"].split(",")))
+        pts = sorted((float(a), float(b)) for a, b in (x.split(":") for x in vals[key].split(",")))
     except (KeyError, ValueError):
         return None
     return pts if len(pts) >= 2 else None
@@ -548,7 +557,7 @@ def precision_cpu_baseline(args, m, o, d, kind, kinds, results, rows, log):
             "sample": "all %d rays, %.1f s wall on %d threads" % (n, wall, threads)}
 
 
-_PROBE_MODES = {"random": 0, "8_lanes": 1, "one_line": 2}
+_PROBE_MODES = {"random": 0, "8_lanes": 1, "one_line": 2, "chain": 3}
 _probe = None
 
 
@@ -606,6 +615,12 @@ def bench_l1probe(args, tetrt, dev, log):
              ("random", 1 << 12, 16, "random 16-B units, 64 KiB set"),
              ("random", 1 << 14, 16, "random 16-B units, 256 KiB set"),
              ("random", 1 << 17, 16, "random 16-B units, 2 MiB set"),
+             ("chain", 1 << 10, 16, "dependent random 16-B units, 16 KiB set"),
+             ("chain", 1 << 11, 16, "dependent random 16-B units, 32 KiB set"),
+             ("chain", 1 << 9, 80, "dependent random 16-B reads in 80-B units, 40 KiB set"),
+             ("chain", 1 << 10, 48, "dependent random 16-B reads in 48-B units, 48 KiB set"),
+             ("chain", 1 << 12, 16, "dependent random 16-B units, 64 KiB set"),
+             ("chain", 1 << 14, 16, "dependent random 16-B units, 256 KiB set"),
              ("8_lanes", 128, 128, "8 lanes per 128-B line, 16 KiB set"),
              ("one_line", 128, 128, "one 128-B line per wave load, 16 KiB set")]
     st = torch.cuda.current_stream()
@@ -624,7 +639,7 @@ def bench_l1probe(args, tetrt, dev, log):
         wave_loads = blocks * 4 * iters
         cycles = t * 1e-3 * CLOCK_HZ
         lines_per_load = {"random": units * (1 - (1 - 1 / units) ** 64) if ub == 128 else None,
-                          "8_lanes": 8, "one_line": 1}[mode]
+                          "chain": None, "8_lanes": 8, "one_line": 1}[mode]
         row = {"case": what, "ms": round(t, 4),
                "lane_loads_per_cu_cycle": round(wave_loads * 64 / N_CUS / cycles, 3),
                "wave_loads_per_cu_cycle": round(wave_loads / N_CUS / cycles, 4)}

@@ -8,7 +8,9 @@
 // cache lines.  The L1 looks lines up at a fixed rate per cycle, so that rate,
 // not the bytes moved, is what such loads are limited by.  This kernel
 // measures it: every lane of every wave issues `iters` independent 16-byte
-// loads whose addresses follow `mode`, and the caller times the launch.
+// loads whose addresses follow `mode` (independent loads, or in mode 3 a chain
+// in which each load waits for the previous one), and the caller times the
+// launch.
 //
 // C-ABI (declared here only; not part of the traversal library's header):
 //   int tetrt_probe_l1(const void* d_buf, uint64_t buf_bytes, int32_t mode,
@@ -19,7 +21,11 @@
 //     start of unit u of `units` units of `unit_bytes` bytes:
 //       mode 0  u pseudo-random per lane (a wave touches up to 64 units);
 //       mode 1  eight consecutive lanes per unit (8 units per wave load);
-//       mode 2  one unit per wave load.
+//       mode 2  one unit per wave load;
+//       mode 3  u pseudo-random per lane as in mode 0, but each load's address
+//               also depends on the value the lane's previous load returned
+//               (a dependent chain per lane, as in a walk).
+//
 //     d_out: device, blocks * 256 * 16 bytes, receives per-lane sums (so the
 //     loads stay).  Enqueued on hip_stream (NULL = default stream).  Returns 0,
 //     -1 for a bad argument (unknown mode, unit_bytes not a multiple of 16,
@@ -39,6 +45,7 @@ namespace {
 constexpr int32_t kRandom = 0;
 constexpr int32_t kEightLanes = 1;
 constexpr int32_t kOneLine = 2;
+constexpr int32_t kChain = 3;
 
 thread_local std::string g_probe_error;
 
@@ -54,6 +61,18 @@ __global__ void __launch_bounds__(256) k_probe_l1(const uint4* __restrict__ buf,
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t x = g * 2654435761u + 12345u;   // per-lane linear congruential sequence
     uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+    if (mode == kChain) {
+        uint32_t dep = 0u;
+        for (int32_t k = 0; k < iters; ++k) {
+            x = x * 1664525u + 1013904223u;
+            const uint32_t u = ((x ^ dep) >> 8) & (units - 1u);
+            const uint4 v = buf[size_t(u) * unit_u4];
+            acc.x += v.x; acc.y ^= v.y; acc.z += v.z; acc.w ^= v.w;
+            dep = v.x;
+        }
+        out[g] = acc;
+        return;
+    }
     for (int32_t k = 0; k < iters; ++k) {
         x = x * 1664525u + 1013904223u;
         uint32_t u;
@@ -73,7 +92,7 @@ extern "C" const char* tetrt_probe_last_error(void) { return g_probe_error.c_str
 extern "C" int tetrt_probe_l1(const void* d_buf, uint64_t buf_bytes, int32_t mode, uint32_t unit_bytes,
                               uint32_t units, int32_t blocks, int32_t iters, void* d_out, void* hip_stream) {
     g_probe_error.clear();
-    if (mode != kRandom && mode != kEightLanes && mode != kOneLine)
+    if (mode != kRandom && mode != kEightLanes && mode != kOneLine && mode != kChain)
         return probe_fail(-1, "tetrt_probe_l1: unknown mode");
     if (unit_bytes < 16 || unit_bytes % 16 || units == 0 || (units & (units - 1u)))
         return probe_fail(-1, "tetrt_probe_l1: unit_bytes must be a multiple of 16, units a power of 2");

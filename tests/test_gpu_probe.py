@@ -11,7 +11,7 @@ def test_probe_l1_sums():
     dev = torch.device("cuda:0")
     buf = torch.ones(1 << 16, dtype=torch.uint8, device=dev)
     blocks, iters = 8, 6
-    for mode, units, ub in (("random", 128, 128), ("8_lanes", 64, 64), ("one_line", 16, 16)):
+    for mode, units, ub in (("random", 128, 128), ("8_lanes", 64, 64), ("one_line", 16, 16), ("chain", 128, 16)):
         out = torch.full((blocks * 256, 4), -1, dtype=torch.int32, device=dev)
         probe_l1(buf, mode, ub, units, blocks, iters, out)
         torch.cuda.synchronize()
