@@ -220,7 +220,7 @@ def test_batch_tune(tetrt, scenes, uploaded):
     if chosen["kernel"] == 1:
         assert chosen["block"] in (64, 128, 256)
     else:
-        assert chosen["queue_chunk"] in (64, 256, 1024) and chosen["refill"] in (8, 32)
+        assert chosen["queue_chunk"] in (64, 256, 1024) and chosen["refill"] in (16, 64)
     _fill(jobs)
     b.launch()
     for k, j in enumerate(jobs):
