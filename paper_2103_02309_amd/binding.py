@@ -108,8 +108,8 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
-        raise ImportError("libtetrt.so is not built (%s); run __graft_entry__.build() or "
-                          "python -m paper_2103_02309_amd.build" % _LIB_PATH)
+        raise ImportError("libtetrt.so is not built (%s); run python -m paper_2103_02309_amd.build"
+                          % _LIB_PATH)
     L = C.CDLL(_LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.tm_last_error.restype = C.c_char_p
