@@ -95,10 +95,10 @@ typedef struct {
     int32_t validate;  /* 1 = check the mesh before packing (recommended) */
     int32_t seed_grid; /* cells per axis of the point-location seed grid; 0 = automatic */
     int64_t bin_rays;  /* rays the handle's own workspace serves (8 bytes each and about
-                          9 KB), allocated here, once; 0 = none.  trace_closest uses it for
-                          binning, the queue kernel and the precision variant's two passes
-                          when the caller passes no workspace of its own.  0 <= bin_rays
-                          < 2^31 */
+                          58 KB), allocated here, once; 0 = none.  trace_closest uses it for
+                          binning, the queue kernel and the precision variant's tie list
+                          and two passes when the caller passes no workspace of its own.
+                          0 <= bin_rays < 2^31 */
 } tm_upload_opts;
 
 /* Sizes of an uploaded mesh (tetmesh_info). */
@@ -149,12 +149,20 @@ typedef struct {
                             interleaved over the dies as they are dispatched) */
     float eps;           /* precision variant, 0 = off.  When > 0 (one lane per ray only), a
                             walk step whose float32 exit-face determinants det(q3, q_i) are
-                            within eps * (|q3|_1 + |q_i|_1) of zero recomputes the projections
-                            and determinants in float64 from the float32 points, basis and
-                            origin; the start tet's exit face is then also found in float64.
-                            With the scene extent 1, eps >= 1e-6 covers float32 rounding */
-    void* workspace;     /* device scratch for binning and for kernel 3's queue
-                            (tetmesh_trace_workspace gives the need), or NULL: the handle's own
+                            within eps * (|q3|_1 + |q_i|_1) of zero is decided in float64
+                            along the ray as given (the sign of d . ((P3 - o) x (P_i - o))
+                            from the float32 points, origin and direction); the start tet,
+                            its exit face and the face's orientation are also found in
+                            float64.  A ray whose float64 decision is an exact tie (a vertex
+                            on the ray, a ray in a face's plane) takes the closest hit by
+                            its definition (every constrained triangle tested in float64,
+                            the lowest id among hits within 1e-12 of the nearest), found by
+                            the whole grid when a workspace holds the tie list, else by the
+                            ray's wave; the results are the same.  With the scene extent 1,
+                            eps >= 1e-6 covers float32 rounding */
+    void* workspace;     /* device scratch for binning, kernel 3's queue and the precision
+                            variant's lists (tetmesh_trace_workspace gives the need), or
+                            NULL: the handle's own
                             workspace (tm_upload_opts.bin_rays) is then used when it is large
                             enough.  A binned trace with neither: sort = 2 or kernel = 3 fails
                             (TM_ERR_ARG), sort = 0 traces the rays unbinned (the same
@@ -263,12 +271,15 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
  * trace_closest, except: opts->workspace must be NULL; a trace that bins its
  * rays (sort = 2, or the automatic rule) puts the binning permutation in a
  * fixed array of the library instead (4 bytes per ray, at most
- * TM_NOALLOC_MAX_BINNED_RAYS rays: more is TM_ERR_ARG).  The array exists once
- * per device and lives until the process ends (64 MiB of device memory on every
- * device the library's kernels have run on); it is looked up, not allocated,
- * on a device's first call.  Every call on a device shares it, so calls that
- * bin and overlap in time on one device (other streams, other threads) race
- * and must be ordered by the caller.  Unbinned traces use no scratch at all.
+ * TM_NOALLOC_MAX_BINNED_RAYS rays: more is TM_ERR_ARG), and the queue kernel's
+ * counters (kernel = 3) and the precision variant's tie list (eps > 0) go to
+ * 64 KiB beside that room.  The array exists once per device and lives until
+ * the process ends (64 MiB + 64 KiB of device memory on every device the
+ * library's kernels have run on); it is looked up, not allocated, on a
+ * device's first call.  Every call on a device shares it, so calls that use it
+ * (binning, kernel 3, eps > 0) and overlap in time on one device (other
+ * streams, other threads) race and must be ordered by the caller.  Other
+ * traces use no scratch at all.
  */
 #define TM_NOALLOC_MAX_BINNED_RAYS (1 << 24)
 int trace_closest_noalloc(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d_dir,
@@ -297,7 +308,7 @@ int tetmesh_bin_rays(tm_mesh m, int64_t n_rays, const float* d_orig, const float
                      const tm_trace_opts* opts, int32_t* d_order, void* hip_stream);
 
 /* tetmesh_trace_workspace -- bytes of device workspace a trace_closest call with
- * these arguments needs (0 when it bins no rays).  d_tmax_present: the d_tmax
+ * these arguments needs (0 when it needs none: no binning, kernel 1 or 2, eps = 0).  d_tmax_present: the d_tmax
  * argument of that call (only tested for NULL).  *bytes host out. */
 int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_present,
                             const tm_trace_opts* opts, int64_t* bytes);

@@ -160,16 +160,23 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
     // (without room for them it runs in one pass, with the same results)
     if (o.passes < 0 || o.passes > 2) return fail(TM_ERR_ARG, "%s: passes must be 0, 1 or 2", name);
     int64_t defer_bytes = (o.eps > 0.0f && o.passes == 2) ? 256 + sort_workspace_bytes(n_rays) : 0;
+    // the one-pass precision variant's tie list (without room for it each wave
+    // resolves its own ties, with the same results)
+    int64_t tie_bytes = (o.eps > 0.0f && o.passes != 2 && o.kernel < 2) ? tie_workspace_bytes() : 0;
     // where it goes: the given fixed workspace, the caller's, or the handle's own;
     // with none of them large enough an explicit sort = 2 or kernel = 3 is an
     // error and the automatic choice traces the rays unbinned
     void* ws = nullptr;
     bool handle_ws = false;
-    while (perm_bytes + queue_bytes + defer_bytes > 0) {
-        const int64_t need = perm_bytes + queue_bytes + defer_bytes;
+    while (perm_bytes + queue_bytes + defer_bytes + tie_bytes > 0) {
+        const int64_t need = perm_bytes + queue_bytes + defer_bytes + tie_bytes;
         const int64_t avail = fixed_ws ? fixed_ws_bytes : (o.workspace ? o.workspace_bytes : m->ws_bytes);
         if (avail < need && defer_bytes > 0) {
             defer_bytes = 0;
+            continue;
+        }
+        if (avail < need && tie_bytes > 0) {
+            tie_bytes = 0;
             continue;
         }
         if (fixed_ws) {
@@ -252,20 +259,22 @@ int trace_impl(tm_mesh_s* m, int64_t n_rays, const float* d_orig, const float* d
         c.defer_count = reinterpret_cast<uint32_t*>(base);
         c.defer_list = reinterpret_cast<int32_t*>(base + 256);
     }
+    c.ties = TieList{};
+    if (tie_bytes > 0) c.ties = tie_list_at(static_cast<char*>(ws) + perm_bytes + queue_bytes + defer_bytes);
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     hipError_t e;
     std::unique_lock<std::mutex> lock(m->ws_mu, std::defer_lock);
-    if (binned) {
-        if (handle_ws) {
-            // the previous trace through the handle's workspace may still be reading
-            // its permutation on another stream: this stream waits for it (stream
-            // order covers the same stream)
-            lock.lock();
-            if (m->ws_used && m->ws_stream != stream) {
-                e = hipStreamWaitEvent(stream, m->ws_done, 0);
-                if (e != hipSuccess) return hip_fail(e, name);
-            }
+    if (handle_ws) {
+        // the previous trace through the handle's workspace (permutation, queue
+        // counters, lists) may still be using it on another stream: this stream
+        // waits for it (stream order covers the same stream)
+        lock.lock();
+        if (m->ws_used && m->ws_stream != stream) {
+            e = hipStreamWaitEvent(stream, m->ws_done, 0);
+            if (e != hipSuccess) return hip_fail(e, name);
         }
+    }
+    if (binned) {
         int32_t* perm = nullptr;
         e = launch_sort(sc, d_orig, d_dir, n_rays, ws, &perm, stream);
         if (e != hipSuccess) return hip_fail(e, "ray binning launch");
@@ -364,7 +373,8 @@ int tetmesh_upload(const float* points, int64_t n_points, const int32_t* tets, c
     if (o.bin_rays > 0) {
         // the handle's binning workspace, allocated once here (traces never allocate)
         // room for binning, the queue kernel and the precision variant's two passes
-        const int64_t need = 2 * tetrt::sort_workspace_bytes(o.bin_rays) + 256 + tetrt::queue_workspace_bytes();
+        const int64_t need = 2 * tetrt::sort_workspace_bytes(o.bin_rays) + 256 + tetrt::queue_workspace_bytes() +
+                             tetrt::tie_workspace_bytes();
         void* p = nullptr;
         hipError_t e = hipMalloc(&p, size_t(need));
         if (e == hipSuccess) {
@@ -457,7 +467,8 @@ int tetmesh_trace_workspace(tm_mesh m, int64_t n_rays, const float* d_tmax_prese
     if (rc != TM_OK) return rc;
     if (o.order) binned = false;
     *bytes = (binned ? tetrt::sort_workspace_bytes(n_rays) : 0) + (o.kernel == 3 ? tetrt::queue_workspace_bytes() : 0) +
-             ((o.eps > 0.0f && o.passes == 2) ? 256 + tetrt::sort_workspace_bytes(n_rays) : 0);
+             ((o.eps > 0.0f && o.passes == 2) ? 256 + tetrt::sort_workspace_bytes(n_rays) : 0) +
+             ((o.eps > 0.0f && o.passes != 2 && o.kernel < 2) ? tetrt::tie_workspace_bytes() : 0);
     return TM_OK;
 }
 

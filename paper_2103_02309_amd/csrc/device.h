@@ -63,6 +63,25 @@ struct Queue {
 };
 constexpr int64_t kQueueCursorBytes = 32 * 4 * 64;   // room for 64 dies
 
+// Rays of the precision variant whose walk meets an exact float64 tie, listed by
+// the walk so that their closest hits by definition (a scan of every constrained
+// triangle) are found by the whole grid rather than by the one wave that met
+// them.  Entries past `cap` are resolved by their wave as before.
+struct TieList {
+    uint32_t* count;            // [1] ties listed (zero when the walk starts); null = no list
+    int32_t* ray;               // [cap] ray index
+    int32_t* steps;             // [cap] walk steps before the tie
+    int32_t* n64;               // [cap] steps decided in float64
+    unsigned long long* tmin;   // [cap] bits of the nearest hit's t (a positive double); +inf: none
+    int32_t* best;              // [cap] the lowest id hit within 1e-12 of it
+    uint32_t cap;
+};
+constexpr uint32_t kTieCap = 2048;
+// Bytes of a tie list of kTieCap entries (with its counter), 256-byte aligned parts.
+int64_t tie_workspace_bytes();
+// Carves a tie list out of `bytes` of device memory at p.
+TieList tie_list_at(void* p);
+
 struct LaunchCfg {
     int32_t block;          // threads per block (64, 128 or 256)
     int32_t kernel;         // 1 = one lane per ray, 2 = persistent lanes, 3 = persistent waves on a queue
@@ -77,6 +96,7 @@ struct LaunchCfg {
     struct Job* queue_job;  // kernel 3: device room for a one-entry job table
     uint32_t* defer_count;  // eps > 0, non-null: two passes (counter and list of deferred rays)
     int32_t* defer_list;    //   list: room for every ray
+    TieList ties;           // eps > 0, one pass: count non-null = ties resolved by the grid
 };
 
 hipError_t launch_trace(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipStream_t s);

@@ -1,7 +1,8 @@
 // trace_closest_noalloc: trace_closest for callers that cannot allocate device
-// memory (code under HIP graph capture, tight serving loops).  Its only scratch
-// is the ray-binning permutation, which lives in `scratch` below, a fixed
-// array of the code object: each device the library runs on holds its own
+// memory (code under HIP graph capture, tight serving loops).  Its scratch --
+// the ray-binning permutation, the queue kernel's counters, the precision
+// variant's tie list -- lives in `scratch` below, a fixed array of the code
+// object: each device the library runs on holds its own
 // copy until the process ends.  Host code never passes the array's name to a
 // kernel (in host code it names a host-side stand-in, not device memory): the
 // device address is looked up once per device with hipGetSymbolAddress and
@@ -21,7 +22,7 @@ constexpr int64_t kScratchRays = TM_NOALLOC_MAX_BINNED_RAYS;
 constexpr int kMaxDevices = 64;
 
 // the binning permutation (4 bytes per binned ray), then room for the queue
-// kernel's counters and job entry
+// kernel's counters and job entry and the precision variant's tie list
 constexpr int64_t kScratchWords = kScratchRays + tetrt::kFixedExtraBytes / 4;
 static __device__ __align__(256) int32_t scratch[kScratchWords];
 

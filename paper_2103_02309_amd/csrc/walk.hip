@@ -290,19 +290,29 @@ __device__ __forceinline__ int exit_slot(float q0x, float q0y, float q1x, float 
     return d0 < 0.0f ? (d2 >= 0.0f ? 1 : 0) : (d1 < 0.0f ? 2 : 0);
 }
 
-// Precision variant: threshold, the origin of the frame, and a count of the
-// steps decided in float64.
+// Precision variant: threshold, the line its float64 decisions follow, and a
+// count of the steps decided in float64.
+// Ray walks (rdir given) decide in float64 along the ray as given: origin and
+// direction are read back for ray `ray` (rare: unsure steps only).  The float32
+// basis leans from the direction by float32 rounding, so float64 decisions in
+// it would answer for a slightly different ray; the unsure test covers that
+// lean as it covers float32 rounding, so the float32 decisions it lets stand
+// hold for the ray as given too.  Location walks (rdir null) follow the segment
+// their float32 basis projects along, from (ox, oy, oz).
 // A float64 decision whose determinant is zero to within float64 rounding is a
 // tie: the ray meets a vertex or edge exactly, or lies in a face plane (a ray
-// along the mesh boundary).  Such ties are flagged (degen) so the ray can be
-// walked again from a slightly moved origin; allow_degen decides them by
-// Algorithm 1's plain inequalities instead.
+// along the mesh boundary).  Such ties are flagged (degen) so the ray can take
+// the closest hit by its definition; allow_degen decides them by Algorithm 1's
+// plain inequalities instead.
 struct Prec {
     float eps;
     float ox, oy, oz;
     int32_t n64;
     bool degen = false;
     bool allow_degen = true;
+    const float* rorig = nullptr;
+    const float* rdir = nullptr;
+    int64_t ray = 0;
 };
 
 // A float64 projection of a point carries an absolute error of a few units of
@@ -317,27 +327,77 @@ __device__ __forceinline__ double det2d(double ax, double ay, double bx, double 
     return ax * by - ay * bx;
 }
 
-__device__ __forceinline__ void project64(const Frame& f, double pox, double poy, float4 p, double& qx,
-                                          double& qy) {
-    qx = fma(double(f.ux), double(p.x), fma(double(f.uy), double(p.y), fma(double(f.uz), double(p.z), -pox)));
-    qy = fma(double(f.vx), double(p.x), fma(double(f.vy), double(p.y), fma(double(f.vz), double(p.z), -poy)));
+// The frame of the float64 decisions: a basis (u, v) and an origin, in double.
+// A point's 2-D coordinates are u.(P - O), v.(P - O): the difference first,
+// exact for float32 inputs of like magnitude.
+struct Frame64 {
+    double ux, uy, uz, vx, vy, vz;
+    double ox, oy, oz;
+};
+
+// The float32 basis, widened (location walks follow the line it projects along).
+__device__ __forceinline__ Frame64 frame64_of(const Frame& f, float ox, float oy, float oz) {
+    return Frame64{double(f.ux), double(f.uy), double(f.uz), double(f.vx), double(f.vy), double(f.vz),
+                   double(ox), double(oy), double(oz)};
 }
 
-// Algorithm 1 on the float64 projections of the kept vertices a0..a2 and P.
+__device__ __forceinline__ void project64(const Frame64& F, float4 p, double& qx, double& qy) {
+    const double rx = double(p.x) - F.ox, ry = double(p.y) - F.oy, rz = double(p.z) - F.oz;
+    qx = fma(F.ux, rx, fma(F.uy, ry, F.uz * rz));
+    qy = fma(F.vx, rx, fma(F.vy, ry, F.vz * rz));
+}
+
+// Along the direction d as given, the 2-D determinant of two projected points
+// a, b is, up to a positive factor, the triple product d . ((a - O) x (b - O)):
+// the projection's basis (u, v) is orthogonal to d with u x v along +d.  So a
+// ray walk decides in float64 with d itself and no basis.  The products are
+// exact for float32 inputs up to the last sums; anything within 1e-14 of the
+// product of the three vectors' 1-norms is a tie.
+__device__ __forceinline__ double triple64(double dx, double dy, double dz, double ax, double ay, double az,
+                                           double bx, double by, double bz, double& scale) {
+    scale = (fabs(dx) + fabs(dy) + fabs(dz)) * (fabs(ax) + fabs(ay) + fabs(az)) * (fabs(bx) + fabs(by) + fabs(bz));
+    return fma(dx, ay * bz - az * by, fma(dy, az * bx - ax * bz, dz * (ax * by - ay * bx)));
+}
+
+// Algorithm 1 on float64 determinants of the kept vertices a0..a2 and P.
+// EXACT: a ray walk (pc.rdir given), decided along the ray as given.
+template <bool EXACT>
 __device__ int exit_slot64(const Mem& M, const Frame& f, Prec& pc, int32_t a0, int32_t a1,
                            int32_t a2, float4 P) {
-    const double pox = fma(double(f.ux), double(pc.ox), fma(double(f.uy), double(pc.oy), double(f.uz) * double(pc.oz)));
-    const double poy = fma(double(f.vx), double(pc.ox), fma(double(f.vy), double(pc.oy), double(f.vz) * double(pc.oz)));
+    if (EXACT) {
+        // a ray walk: along the ray as given
+        const float* op = pc.rorig + 3 * pc.ray;
+        const float* dp = pc.rdir + 3 * pc.ray;
+        const double ox = op[0], oy = op[1], oz = op[2];
+        const double dx = dp[0], dy = dp[1], dz = dp[2];
+        const double rx = double(P.x) - ox, ry = double(P.y) - oy, rz = double(P.z) - oz;
+        // d . (r3 x r_k) = (d x r3) . r_k: the cross product once for the three
+        const double cx = dy * rz - dz * ry, cy = dz * rx - dx * rz, cz = dx * ry - dy * rx;
+        const double s3 = (fabs(dx) + fabs(dy) + fabs(dz)) * (fabs(rx) + fabs(ry) + fabs(rz));
+        double d[3], sc[3];
+        const int32_t ids[3] = {a0, a1, a2};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float4 Q = load_pt(M, uint32_t(ids[k]));
+            const double qx = double(Q.x) - ox, qy = double(Q.y) - oy, qz = double(Q.z) - oz;
+            d[k] = fma(cx, qx, fma(cy, qy, cz * qz));
+            sc[k] = s3 * (fabs(qx) + fabs(qy) + fabs(qz));
+        }
+        if (!pc.allow_degen)
+            pc.degen |= fabs(d[0]) <= kTie64 * sc[0] || fabs(d[1]) <= kTie64 * sc[1] || fabs(d[2]) <= kTie64 * sc[2];
+        return d[0] < 0.0 ? (d[2] >= 0.0 ? 1 : 0) : (d[1] < 0.0 ? 2 : 0);
+    }
+    const Frame64 F = frame64_of(f, pc.ox, pc.oy, pc.oz);
     double x0, y0, x1, y1, x2, y2, x3, y3;
-    project64(f, pox, poy, load_pt(M, uint32_t(a0)), x0, y0);
-    project64(f, pox, poy, load_pt(M, uint32_t(a1)), x1, y1);
-    project64(f, pox, poy, load_pt(M, uint32_t(a2)), x2, y2);
-    project64(f, pox, poy, P, x3, y3);
+    project64(F, load_pt(M, uint32_t(a0)), x0, y0);
+    project64(F, load_pt(M, uint32_t(a1)), x1, y1);
+    project64(F, load_pt(M, uint32_t(a2)), x2, y2);
+    project64(F, P, x3, y3);
     const double d0 = det2d(x3, y3, x0, y0);
     const double d1 = det2d(x3, y3, x1, y1);
     const double d2 = det2d(x3, y3, x2, y2);
     if (!pc.allow_degen) {
-        const double S = kTie64 * (1.0 + fabs(pox) + fabs(poy));
+        const double S = kTie64 * (1.0 + fabs(F.ox) + fabs(F.oy) + fabs(F.oz));
         const double s3 = fabs(x3) + fabs(y3);
         pc.degen |= fabs(d0) <= S * (s3 + fabs(x0) + fabs(y0)) ||
                     fabs(d1) <= S * (s3 + fabs(x1) + fabs(y1)) ||
@@ -378,16 +438,27 @@ __device__ __forceinline__ void make_ccw(Walk& w) {
 // every later exit decision.
 // Returns true when the orientation is a float64 tie (the face's projection is
 // a segment: its plane contains the ray direction).
-__device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, float Xz, float4 A,
-                                           float4 B, float4 C, Walk& w) {
-    const double pox = fma(double(f.ux), double(Xx), fma(double(f.uy), double(Xy), double(f.uz) * double(Xz)));
-    const double poy = fma(double(f.vx), double(Xx), fma(double(f.vy), double(Xy), double(f.vz) * double(Xz)));
-    double x0, y0, x1, y1, x2, y2;
-    project64(f, pox, poy, A, x0, y0);
-    project64(f, pox, poy, B, x1, y1);
-    project64(f, pox, poy, C, x2, y2);
-    const double ex = x1 - x0, ey = y1 - y0, fx = x2 - x0, fy = y2 - y0;
-    const double o = det2d(ex, ey, fx, fy);
+// dir (ray walks): the orientation is that of the projection along the ray's
+// direction as given, the sign of dir . ((B - A) x (C - A)); else along the
+// float32 basis of f from X.
+__device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, float Xz, const float* dir,
+                                           float4 A, float4 B, float4 C, Walk& w) {
+    double o, tol;
+    if (dir) {
+        double sc;
+        o = triple64(double(dir[0]), double(dir[1]), double(dir[2]), double(B.x) - A.x, double(B.y) - A.y,
+                     double(B.z) - A.z, double(C.x) - A.x, double(C.y) - A.y, double(C.z) - A.z, sc);
+        tol = kTie64 * sc;
+    } else {
+        const Frame64 F = frame64_of(f, Xx, Xy, Xz);
+        double x0, y0, x1, y1, x2, y2;
+        project64(F, A, x0, y0);
+        project64(F, B, x1, y1);
+        project64(F, C, x2, y2);
+        const double ex = x1 - x0, ey = y1 - y0, fx = x2 - x0, fy = y2 - y0;
+        o = det2d(ex, ey, fx, fy);
+        tol = kTie64 * (1.0 + fabs(F.ox) + fabs(F.oy) + fabs(F.oz)) * (fabs(ex) + fabs(ey) + fabs(fx) + fabs(fy));
+    }
     const bool sw = o < 0.0;
     const int32_t a1 = w.a1, a2 = w.a2;
     const float q1x = w.q1x, q1y = w.q1y, q2x = w.q2x, q2y = w.q2y, e1 = w.e1, e2 = w.e2;
@@ -395,7 +466,7 @@ __device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, f
     w.q1x = sw ? q2x : q1x; w.q2x = sw ? q1x : q2x;
     w.q1y = sw ? q2y : q1y; w.q2y = sw ? q1y : q2y;
     w.e1 = sw ? e2 : e1; w.e2 = sw ? e1 : e2;
-    return fabs(o) <= kTie64 * (1.0 + fabs(pox) + fabs(poy)) * (fabs(ex) + fabs(ey) + fabs(fx) + fabs(fy));
+    return fabs(o) <= tol;
 }
 
 // One step of the walk (Algorithm 1 with Algorithms 4-5 or 6-7), branch-free
@@ -411,7 +482,9 @@ __device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, f
 // load return zeros without touching memory.
 // unsure (given, with PREC false): the step only tests whether its float32
 // decision is unsure -- the test of the precision variant -- and reports it.
-template <bool DEPTH, int LAYOUT, bool PREC, bool LINK = false, bool PIPE = false>
+// EXACT (a ray walk of the precision variant): unsure steps are decided along
+// the ray as given (pc.rorig, pc.rdir), else along the float32 basis.
+template <bool DEPTH, int LAYOUT, bool PREC, bool LINK = false, bool PIPE = false, bool EXACT = false>
 __device__ __forceinline__ void walk_step_rec(const Mem& M, const Frame& f, const Depth& g, Walk& w,
                                               Prec& pc, const Rec& R, Rec* ahead, bool* unsure_out = nullptr) {
     const uint32_t tet = w.next;
@@ -453,7 +526,7 @@ __device__ __forceinline__ void walk_step_rec(const Mem& M, const Frame& f, cons
         if (U) {
             int e = 0;
             if (unsure) {
-                e = exit_slot64(M, f, pc, w.a0, w.a1, w.a2, P);
+                e = exit_slot64<EXACT>(M, f, pc, w.a0, w.a1, w.a2, P);
                 ++pc.n64;
             }
             S1 = (S1 & ~U) | lanes(unsure && e == 1);
@@ -520,7 +593,9 @@ __device__ __forceinline__ void walk_step(const Mem& M, const Frame& f, const De
 // Fills the walk state (face ids, 2-D points in frame f, depths in g, the
 // neighbour field) and returns s (+inf when no face is front-facing).
 // The plane tests run in T: float, or double in the precision variant.
-template <bool DEPTH, int LAYOUT, typename T>
+// EXACT (ray walks of the precision variant): D is the ray's direction as given,
+// and the float64 tests and orientation follow it (see Prec).
+template <bool DEPTH, int LAYOUT, typename T, bool EXACT = false>
 __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const int32_t v[4],
                               float Xx, float Xy, float Xz, float Dx, float Dy, float Dz,
                               const Frame& f, const Depth& g, Walk& w, bool* degen = nullptr) {
@@ -533,12 +608,13 @@ __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const
         ry[k] = T(P[k].y) - T(Xy);
         rz[k] = T(P[k].z) - T(Xz);
     }
-    // In float64 (precision variant) the plane tests use the direction the walk
-    // actually projects along, u x v of the float32 basis, rather than D: the two
-    // differ by float32 rounding, and for a ray that grazes an edge the start face
-    // chosen for D need not surround the origin in the walk's projection.
+    // In float64 a location walk's plane tests use the direction its walk
+    // projects along, u x v of the float32 basis, rather than D: the two differ
+    // by float32 rounding, and for a segment that grazes an edge the start face
+    // chosen for D need not surround the origin in the walk's projection.  A
+    // ray walk's float64 decisions follow D itself.
     T ex = T(Dx), ey = T(Dy), ez = T(Dz);
-    if (std::is_same<T, double>::value) {
+    if (std::is_same<T, double>::value && !EXACT) {
         ex = T(f.uy) * T(f.vz) - T(f.uz) * T(f.vy);
         ey = T(f.uz) * T(f.vx) - T(f.ux) * T(f.vz);
         ez = T(f.ux) * T(f.vy) - T(f.uy) * T(f.vx);
@@ -587,7 +663,8 @@ __device__ float start_in_tet(const DevMesh& m, const Mem& M, int32_t tet, const
     if (LAYOUT == kTet32N) w.vxn = int32_t(pick4(R.w0, R.w1, R.w2, R.w3, r));
     w.cur = tet;
     if (std::is_same<T, double>::value) {
-        const bool tie = make_ccw64(f, Xx, Xy, Xz, PA, PB, PC, w);
+        const float D[3] = {Dx, Dy, Dz};
+        const bool tie = make_ccw64(f, Xx, Xy, Xz, EXACT ? D : nullptr, PA, PB, PC, w);
         if (degen) *degen = tie;
     } else {
         make_ccw(w);
@@ -746,6 +823,7 @@ struct Knobs {
     float eps;                // precision variant threshold (PREC kernels)
     uint32_t xcd_blocks;      // block renumbering for the XCDs: 0 = one contiguous range per
                               // XCD, > 0 = runs of this many consecutive blocks per XCD
+    TieList ties;             // PREC one-pass kernel: where its ties are listed (count null: none)
 };
 
 __device__ __forceinline__ void write_result(const RayArgs& r, int64_t i, int32_t code, float t,
@@ -766,17 +844,14 @@ __device__ __forceinline__ void write_code(const RayArgs& r, int64_t i, int32_t 
 }
 
 // Set-up of ray i.  Returns true when the ray needs walking (state in s);
-// false when its result is already written.  Precision variant: `moved`, when
-// given, replaces the ray's origin, *degen reports a float64 tie in the
-// orientation of the start face, and *lost that no start tet was found (the
-// origin lies on the mesh boundary, or no face of the start tet faces the ray).
+// false when its result is already written.  Precision variant: *degen reports
+// a float64 tie in the orientation of the start face, and *lost that no start
+// tet was found (the origin lies on the mesh boundary, or no face of the start
+// tet faces the ray).
 template <bool TMAX, int LAYOUT, bool PREC>
 __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t i, Ray& s,
-                          float eps, const float* moved = nullptr, bool* degen = nullptr,
-                          bool* lost = nullptr) {
-    const float ox = moved ? moved[0] : r.orig[3 * i];
-    const float oy = moved ? moved[1] : r.orig[3 * i + 1];
-    const float oz = moved ? moved[2] : r.orig[3 * i + 2];
+                          float eps, bool* degen = nullptr, bool* lost = nullptr) {
+    const float ox = r.orig[3 * i], oy = r.orig[3 * i + 1], oz = r.orig[3 * i + 2];
     const float dx = r.dir[3 * i], dy = r.dir[3 * i + 1], dz = r.dir[3 * i + 2];
     s.tmax = (TMAX && r.tmax) ? r.tmax[i] : INFINITY;
     s.steps = 0;
@@ -810,7 +885,8 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
         project(s.f, PC, s.w.q2x, s.w.q2y);
         if (TMAX) { s.w.e0 = depth(s.g, PA); s.w.e1 = depth(s.g, PB); s.w.e2 = depth(s.g, PC); }
         if (PREC) {
-            const bool tie = make_ccw64(s.f, ox, oy, oz, PA, PB, PC, s.w);
+            const float D[3] = {dx, dy, dz};
+            const bool tie = make_ccw64(s.f, ox, oy, oz, D, PA, PB, PC, s.w);
             if (degen) *degen = tie;
         } else {
             make_ccw(s.w);
@@ -840,7 +916,7 @@ __device__ bool setup_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int6
     set_origin(s.f, ox, oy, oz);
     if (TMAX) set_depth(s.g, dx, dy, dz, ox, oy, oz);
     using T = typename std::conditional<PREC, double, float>::type;
-    const float sx = start_in_tet<TMAX, LAYOUT, T>(m, M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w, degen);
+    const float sx = start_in_tet<TMAX, LAYOUT, T, PREC>(m, M, tet, v, ox, oy, oz, dx, dy, dz, s.f, s.g, s.w, degen);
     if (!(sx < INFINITY)) {
         if (lost) *lost = true;
         write_code(r, i, TM_RAY_INVALID, 0);
@@ -1039,6 +1115,31 @@ __device__ __forceinline__ bool on_bounds(const DevMesh& m, float px, float py, 
     return on;
 }
 
+// The result of ray k from the closest hit by definition h: a miss, or the hit
+// with its front and back tets (the front one on the side the ray comes from).
+template <bool TMAX>
+__device__ void write_def_hit(const DevMesh& m, const Mem& M, const RayArgs& r, int64_t k, const DefHit& h,
+                              int32_t steps, int32_t n64) {
+    if (h.tri < 0) {
+        write_code(r, k, TM_RAY_MISS, steps, n64);
+        return;
+    }
+    int32_t front = -1, back = -1;
+    if (r.hit_tets) {
+        const double dx = r.dir[3 * k], dy = r.dir[3 * k + 1], dz = r.dir[3 * k + 2];
+        const int4 fv = reinterpret_cast<const int4*>(m.cfv)[h.tri];
+        const int4 ft = reinterpret_cast<const int4*>(m.cft)[h.tri];
+        const float4 A = load_pt(M, uint32_t(fv.x)), B = load_pt(M, uint32_t(fv.y)), C = load_pt(M, uint32_t(fv.z));
+        const double e1x = double(B.x) - A.x, e1y = double(B.y) - A.y, e1z = double(B.z) - A.z;
+        const double e2x = double(C.x) - A.x, e2y = double(C.y) - A.y, e2z = double(C.z) - A.z;
+        const double nd = (e1y * e2z - e1z * e2y) * dx + (e1z * e2x - e1x * e2z) * dy + (e1x * e2y - e1y * e2x) * dz;
+        const int32_t f = nd > 0.0 ? ft.y : ft.x, b = nd > 0.0 ? ft.x : ft.y;
+        front = f >= 0 ? m.t_new2old[f] : -1;
+        back = b >= 0 ? m.t_new2old[b] : -1;
+    }
+    write_result(r, k, h.tri, float(h.t), float(h.u), float(h.v), front, back, steps, n64);
+}
+
 // The ties of a wave's lanes (ballot), one after the other, each by the whole
 // wave; lane `tie` writes its ray's result.  Every lane of the wave must call it.
 template <bool TMAX>
@@ -1054,28 +1155,113 @@ __device__ void resolve_ties(const DevMesh& m, const Mem& M, const RayArgs& r, b
         const double tmax = (TMAX && r.tmax) ? double(r.tmax[k]) : INFINITY;
         const int32_t sf = r.start_face ? r.start_face[k] : -1;
         const DefHit h = wave_closest_hit(m, M, ox, oy, oz, dx, dy, dz, tmax, sf);
-        if (int(threadIdx.x & 63) == l) {
-            if (h.tri < 0) {
-                write_code(r, k, TM_RAY_MISS, steps, n64);
-            } else {
-                int32_t front = -1, back = -1;
-                if (r.hit_tets) {
-                    // the ray comes from the side its direction points away from
-                    const int4 fv = reinterpret_cast<const int4*>(m.cfv)[h.tri];
-                    const int4 ft = reinterpret_cast<const int4*>(m.cft)[h.tri];
-                    const float4 A = load_pt(M, uint32_t(fv.x)), B = load_pt(M, uint32_t(fv.y)),
-                                 C = load_pt(M, uint32_t(fv.z));
-                    const double e1x = double(B.x) - A.x, e1y = double(B.y) - A.y, e1z = double(B.z) - A.z;
-                    const double e2x = double(C.x) - A.x, e2y = double(C.y) - A.y, e2z = double(C.z) - A.z;
-                    const double nd = (e1y * e2z - e1z * e2y) * dx + (e1z * e2x - e1x * e2z) * dy +
-                                      (e1x * e2y - e1y * e2x) * dz;
-                    const int32_t f = nd > 0.0 ? ft.y : ft.x, b = nd > 0.0 ? ft.x : ft.y;
-                    front = f >= 0 ? m.t_new2old[f] : -1;
-                    back = b >= 0 ? m.t_new2old[b] : -1;
-                }
-                write_result(r, k, h.tri, float(h.t), float(h.u), float(h.v), front, back, steps, n64);
-            }
+        if (int(threadIdx.x & 63) == l) write_def_hit<TMAX>(m, M, r, k, h, steps, n64);
+    }
+}
+
+// The ties of a wave: listed in L when it is given (entries past its capacity,
+// and every tie without a list, are resolved by the wave itself).  Every lane of
+// the wave must call it.
+template <bool TMAX>
+__device__ void list_or_resolve_ties(const DevMesh& m, const Mem& M, const RayArgs& r, const TieList& L, bool tie,
+                                     int64_t i, int32_t steps, int32_t n64) {
+    bool own = tie;
+    const uint64_t T = lanes(tie);
+    if (L.count && T) {
+        const int lead = __builtin_ctzll(T);
+        uint32_t base = 0;
+        if (int(threadIdx.x & 63) == lead) base = atomicAdd(L.count, uint32_t(__popcll(T)));
+        base = __builtin_amdgcn_readlane(base, lead);
+        const uint32_t slot = base + __builtin_amdgcn_mbcnt_hi(uint32_t(T >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(T), 0u));
+        if (tie && slot < L.cap) {
+            L.ray[slot] = int32_t(i);
+            L.steps[slot] = steps;
+            L.n64[slot] = n64;
+            L.tmin[slot] = 0x7FF0000000000000ull;   // +inf
+            L.best[slot] = 0x7FFFFFFF;
+            own = false;
         }
+    }
+    resolve_ties<TMAX>(m, M, r, own, i, steps, n64);
+}
+
+// Grid-wide closest hit by definition of the listed ties: work item k * S + s
+// scans slice s of the constrained triangles (kTieSlice each) for tie k.  Pass 0
+// takes the nearest t (atomic minimum on its bits), pass 1 the lowest id hit
+// within 1e-12 of it; the same rules as wave_closest_hit, so the results are
+// those the wave would write.
+constexpr int kTieSlice = 1024;
+
+template <bool TMAX, int LAYOUT>
+__global__ void __launch_bounds__(256) k_tie_scan(DevMesh m, RayArgs r, TieList L, int32_t pass) {
+    __shared__ double red_t[4];
+    __shared__ int32_t red_i[4];
+    const Mem M = make_mem<LAYOUT>(m);
+    const int64_t n = min(*L.count, L.cap);
+    const int64_t slices = (int64_t(m.ntri) + kTieSlice - 1) / kTieSlice;
+    const int4* cfv = reinterpret_cast<const int4*>(m.cfv);
+    const int w = int(threadIdx.x >> 6);
+    for (int64_t it = blockIdx.x; it < n * slices; it += gridDim.x) {
+        const int64_t k = it / slices;
+        const int32_t f0 = int32_t((it % slices) * kTieSlice);
+        const int32_t f1 = min(f0 + kTieSlice, m.ntri);
+        const int64_t ray = L.ray[k];
+        const double ox = r.orig[3 * ray], oy = r.orig[3 * ray + 1], oz = r.orig[3 * ray + 2];
+        const double dx = r.dir[3 * ray], dy = r.dir[3 * ray + 1], dz = r.dir[3 * ray + 2];
+        const double tmax = (TMAX && r.tmax) ? double(r.tmax[ray]) : INFINITY;
+        const int32_t sf = r.start_face ? r.start_face[ray] : -1;
+        if (pass == 0) {
+            double best = INFINITY;
+            for (int32_t f = f0 + int32_t(threadIdx.x); f < f1; f += 256) {
+                double t, u, v;
+                if (f != sf && mt64(M, cfv[f], ox, oy, oz, dx, dy, dz, t, u, v) && t > 0.0 && t <= tmax)
+                    best = fmin(best, t);
+            }
+            best = wave_min(best);
+            if ((threadIdx.x & 63) == 0) red_t[w] = best;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const double b = fmin(fmin(red_t[0], red_t[1]), fmin(red_t[2], red_t[3]));
+                if (b < INFINITY) atomicMin(L.tmin + k, static_cast<unsigned long long>(__double_as_longlong(b)));
+            }
+            __syncthreads();
+        } else {
+            const double tmin = __longlong_as_double(static_cast<long long>(L.tmin[k]));
+            if (!(tmin < INFINITY)) continue;   // the same for the whole block
+            int32_t id = 0x7FFFFFFF;
+            for (int32_t f = f0 + int32_t(threadIdx.x); f < f1; f += 256) {
+                double t, u, v;
+                if (f != sf && mt64(M, cfv[f], ox, oy, oz, dx, dy, dz, t, u, v) && t > 0.0 && t <= tmax &&
+                    t <= tmin + 1e-12)
+                    id = min(id, f);
+            }
+            id = wave_min_i(id);
+            if ((threadIdx.x & 63) == 0) red_i[w] = id;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int32_t b = min(min(red_i[0], red_i[1]), min(red_i[2], red_i[3]));
+                if (b != 0x7FFFFFFF) atomicMin(L.best + k, b);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// The listed ties' results, from the hits found by the scans.
+template <bool TMAX, int LAYOUT>
+__global__ void __launch_bounds__(256) k_tie_write(DevMesh m, RayArgs r, TieList L) {
+    const Mem M = make_mem<LAYOUT>(m);
+    const int64_t n = min(*L.count, L.cap);
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t ray = L.ray[k];
+        DefHit h{TM_RAY_MISS, NAN, NAN, NAN};
+        if (L.best[k] != 0x7FFFFFFF) {
+            h.tri = L.best[k];
+            const double ox = r.orig[3 * ray], oy = r.orig[3 * ray + 1], oz = r.orig[3 * ray + 2];
+            const double dx = r.dir[3 * ray], dy = r.dir[3 * ray + 1], dz = r.dir[3 * ray + 2];
+            (void)mt64(M, reinterpret_cast<const int4*>(m.cfv)[h.tri], ox, oy, oz, dx, dy, dz, h.t, h.u, h.v);
+        }
+        write_def_hit<TMAX>(m, M, r, ray, h, L.steps[k], L.n64[k]);
     }
 }
 
@@ -1091,7 +1277,7 @@ __device__ __forceinline__ bool trace_prec(const DevMesh& m, const Mem& M, const
     bool degen = false, lost = false;
     steps_out = 0;
     n64_out = 0;
-    if (!setup_ray<TMAX, LAYOUT, true>(m, M, r, i, s, eps, nullptr, &degen, &lost)) {
+    if (!setup_ray<TMAX, LAYOUT, true>(m, M, r, i, s, eps, &degen, &lost)) {
         // no start tet: an origin on the boundary takes the definition (the result of
         // setup_ray, TM_RAY_INVALID, stands otherwise)
         if (!lost || !on_bounds(m, r.orig[3 * i], r.orig[3 * i + 1], r.orig[3 * i + 2])) return false;
@@ -1102,7 +1288,11 @@ __device__ __forceinline__ bool trace_prec(const DevMesh& m, const Mem& M, const
         if (DEFER) { *deferred = true; return false; }
         return true;
     }
-    Prec pc{eps, r.orig[3 * i], r.orig[3 * i + 1], r.orig[3 * i + 2], 0};
+    // float64 decisions along the ray as given (read back when a step is unsure)
+    Prec pc{eps, 0.0f, 0.0f, 0.0f, 0};
+    pc.rorig = r.orig;
+    pc.rdir = r.dir;
+    pc.ray = i;
     pc.allow_degen = false;
     // the pipelined form of walk_ray (next record loaded inside the step)
     if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
@@ -1113,7 +1303,7 @@ __device__ __forceinline__ bool trace_prec(const DevMesh& m, const Mem& M, const
             walk_step_rec<TMAX, LAYOUT, false, true, true>(M, s.f, s.g, s.w, pc, R, &R, &unsure);
             if (unsure) break;
         } else {
-            walk_step_rec<TMAX, LAYOUT, true, true, true>(M, s.f, s.g, s.w, pc, R, &R);
+            walk_step_rec<TMAX, LAYOUT, true, true, true, true>(M, s.f, s.g, s.w, pc, R, &R);
         }
         ++s.steps;
     }
@@ -1146,7 +1336,7 @@ k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     const bool valid = j < r.n && uint64_t(i) < uint64_t(r.n);
     int32_t steps = 0, n64 = 0;
     const bool tie = valid && trace_prec<TMAX, LAYOUT, false>(m, M, r, i, kn.eps, steps, n64, nullptr);
-    resolve_ties<TMAX>(m, M, r, tie, i, steps, n64);
+    list_or_resolve_ties<TMAX>(m, M, r, kn.ties, tie, i, steps, n64);
 }
 
 // Two-pass precision variant, first pass: the float32 walk with the unsure test
@@ -1539,8 +1729,19 @@ void launch_trace_t(const DevMesh& m, const RayArgs& r, const LaunchCfg& c, hipS
         hipLaunchKernelGGL((k_trace_listed<TMAX, LAYOUT>), dim3(unsigned(grid)), dim3(256), 0, s, m, r, kn,
                            c.defer_count, c.defer_list);
     } else if (c.eps > 0.0f) {
+        // ties go to a list (when there is room for one), whose closest hits by
+        // definition the whole grid then finds: a scan pass for the nearest t, one
+        // for the lowest id at it, and the results
+        if (c.ties.count) hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, c.ties.count, 1);
         hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, true, true>), dim3(unsigned(simple_grid)), dim3(block), 0,
-                           s, m, r, uint32_t(std::max(1, c.xcds)), Knobs{c.eps, uint32_t(c.xcd_blocks)});
+                           s, m, r, uint32_t(std::max(1, c.xcds)), Knobs{c.eps, uint32_t(c.xcd_blocks), c.ties});
+        if (c.ties.count) {
+            const unsigned grid = unsigned(std::max(1, c.cus) * 8);
+            hipLaunchKernelGGL((k_tie_scan<TMAX, LAYOUT>), dim3(grid), dim3(256), 0, s, m, r, c.ties, 0);
+            hipLaunchKernelGGL((k_tie_scan<TMAX, LAYOUT>), dim3(grid), dim3(256), 0, s, m, r, c.ties, 1);
+            hipLaunchKernelGGL((k_tie_write<TMAX, LAYOUT>), dim3((kTieCap + 255) / 256), dim3(256), 0, s, m, r,
+                               c.ties);
+        }
     } else if (r.steps) {
         hipLaunchKernelGGL((k_trace<TMAX, LAYOUT, false, true>), dim3(unsigned(simple_grid)), dim3(block), 0,
                            s, m, r, uint32_t(std::max(1, c.xcds)), Knobs{0.0f, uint32_t(c.xcd_blocks)});
@@ -1594,6 +1795,23 @@ hipError_t launch_trace_batch(const Job* d_jobs, int32_t n_jobs, int64_t total_b
 }
 
 int64_t queue_workspace_bytes() { return kQueueCursorBytes + (int64_t(sizeof(Job)) + 255) / 256 * 256; }
+
+// [count: 256 B][ray, steps, n64, best: 4 B each][tmin: 8 B], each part 256-byte aligned
+int64_t tie_workspace_bytes() { return 256 + 4 * (int64_t(kTieCap) * 4) + int64_t(kTieCap) * 8; }
+
+TieList tie_list_at(void* p) {
+    char* b = static_cast<char*>(p);
+    const int64_t q = int64_t(kTieCap) * 4;
+    TieList L;
+    L.count = reinterpret_cast<uint32_t*>(b);
+    L.ray = reinterpret_cast<int32_t*>(b + 256);
+    L.steps = reinterpret_cast<int32_t*>(b + 256 + q);
+    L.n64 = reinterpret_cast<int32_t*>(b + 256 + 2 * q);
+    L.best = reinterpret_cast<int32_t*>(b + 256 + 3 * q);
+    L.tmin = reinterpret_cast<unsigned long long*>(b + 256 + 4 * q);
+    L.cap = kTieCap;
+    return L;
+}
 
 hipError_t launch_trace_batch_queue(const Job* d_jobs, int32_t n_jobs, const Queue& q, int32_t layout,
                                     bool steps, int32_t cus, hipStream_t s) {

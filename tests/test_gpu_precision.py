@@ -101,7 +101,10 @@ def test_precision_sweep(stress, eps):
 def test_two_pass_equals_one_pass(stress, eps):
     """The two-pass form (a float32 walk that defers its unsure rays to a list, then
     the float64-capable kernel on the list; passes = 2 with a workspace) gives
-    the one-pass precision variant's results bit for bit, also in bin order."""
+    the one-pass precision variant's results bit for bit, also in bin order; and
+    the one-pass form with a workspace (its ties listed and resolved by the whole
+    grid, the list overflowing into the waves on this set) gives those of the
+    one-pass form without one (every tie resolved by its wave)."""
     import paper_2103_02309_amd as tetrt
     m, om, mesh, o, d, kind, ref = stress
     n = len(o)
@@ -116,9 +119,14 @@ def test_two_pass_equals_one_pass(stress, eps):
                                     hit_tets=one["hit_tets"], steps=one["steps"], fp64_steps=one["fp64_steps"],
                                     eps=eps, max_steps=20000)
         torch.cuda.synchronize()
+        listed = mesh.trace(O, D, tmax=tmax, want_steps=True, want_tets=True, want_fp64=True, eps=eps,
+                            max_steps=20000)
+        torch.cuda.synchronize()
         for k in two:
             a, b = two[k].cpu().numpy(), one[k].cpu().numpy()
             assert np.array_equal(a, b, equal_nan=True), (eps, tmax is None, k, int((a != b).sum()))
+            c = listed[k].cpu().numpy()
+            assert np.array_equal(c, b, equal_nan=True), ("listed ties", eps, tmax is None, k, int((c != b).sum()))
         binned = mesh.trace(O, D, tmax=tmax, want_steps=True, want_tets=True, want_fp64=True, eps=eps,
                             max_steps=20000, sort=2, passes=2)
         torch.cuda.synchronize()

@@ -1,6 +1,7 @@
 """trace_closest_noalloc (for callers that cannot allocate) against
-trace_closest: the same kernels, with the binning permutation in the library's
-fixed per-device array instead of a caller workspace.  Two calls in a row, the
+trace_closest: the same kernels, with the binning permutation (and the
+precision variant's tie list) in the library's fixed per-device array instead
+of a caller workspace.  Two calls in a row, the
 second smaller, must both give trace_closest's results bit for bit; sizes
 beyond the array and a workspace argument are refused."""
 import numpy as np
@@ -42,16 +43,17 @@ def _noalloc(tetrt, mesh, O, D, T, out, **opts):
                                         hit_tets=out.get("hit_tets"), steps=out.get("steps"), **opts)
 
 
-@pytest.mark.parametrize("sort", [2, 0])
-def test_noalloc_matches_trace_closest(mesh, sort):
+@pytest.mark.parametrize("kw", [dict(sort=2), dict(sort=0), dict(sort=2, eps=1e-6)])
+def test_noalloc_matches_trace_closest(mesh, kw):
+    """eps > 0: the precision variant, with its tie list in the fixed array too."""
     tetrt, h = mesh
     for n, seed in ((300_000, 81), (70_001, 82)):   # the second call smaller, ragged
         O, D, T = _rays(n, seed)
-        ref = _host(h.trace(O, D, tmax=T, want_tets=True, want_steps=True, sort=sort))
+        ref = _host(h.trace(O, D, tmax=T, want_tets=True, want_steps=True, **kw))
         out = tetrt.outputs(n, "cuda:0", want_tets=True, want_steps=True)
         for v in out.values():
             v.fill_(-7)
-        _noalloc(tetrt, h, O, D, T, out, sort=sort)
+        _noalloc(tetrt, h, O, D, T, out, **kw)
         got = _host(out)
         for k in ref:
             assert np.array_equal(got[k], ref[k], equal_nan=True), (n, k)
