@@ -292,12 +292,13 @@ __device__ __forceinline__ int exit_slot(float q0x, float q0y, float q1x, float 
 
 // Precision variant: threshold, the line its float64 decisions follow, and a
 // count of the steps decided in float64.
-// Ray walks (rdir given) decide in float64 along the ray as given: origin and
-// direction are read back for ray `ray` (rare: unsure steps only).  The float32
+// Ray walks (ray6 given) decide in float64 along the ray as given: origin and
+// direction are read back from the lane's copy in LDS (ray6[k * kRayStash], k =
+// 0..5; rare: unsure steps only).  The float32
 // basis leans from the direction by float32 rounding, so float64 decisions in
 // it would answer for a slightly different ray; the unsure test covers that
 // lean as it covers float32 rounding, so the float32 decisions it lets stand
-// hold for the ray as given too.  Location walks (rdir null) follow the segment
+// hold for the ray as given too.  Location walks (ray6 null) follow the segment
 // their float32 basis projects along, from (ox, oy, oz).
 // A float64 decision whose determinant is zero to within float64 rounding is a
 // tie: the ray meets a vertex or edge exactly, or lies in a face plane (a ray
@@ -310,10 +311,11 @@ struct Prec {
     int32_t n64;
     bool degen = false;
     bool allow_degen = true;
-    const float* rorig = nullptr;
-    const float* rdir = nullptr;
-    int64_t ray = 0;
+    const float* ray6 = nullptr;
 };
+
+// Stride of the per-lane ray copies in LDS (threads per block at most).
+constexpr int kRayStash = 256;
 
 // A float64 projection of a point carries an absolute error of a few units of
 // float64 rounding of the coordinates (about 1e-16 of the scene's size S), so a
@@ -360,16 +362,15 @@ __device__ __forceinline__ double triple64(double dx, double dy, double dz, doub
 }
 
 // Algorithm 1 on float64 determinants of the kept vertices a0..a2 and P.
-// EXACT: a ray walk (pc.rdir given), decided along the ray as given.
+// EXACT: a ray walk (pc.ray6 given), decided along the ray as given.
 template <bool EXACT>
 __device__ int exit_slot64(const Mem& M, const Frame& f, Prec& pc, int32_t a0, int32_t a1,
                            int32_t a2, float4 P) {
     if (EXACT) {
         // a ray walk: along the ray as given
-        const float* op = pc.rorig + 3 * pc.ray;
-        const float* dp = pc.rdir + 3 * pc.ray;
-        const double ox = op[0], oy = op[1], oz = op[2];
-        const double dx = dp[0], dy = dp[1], dz = dp[2];
+        const float* st = pc.ray6;
+        const double ox = st[0], oy = st[kRayStash], oz = st[2 * kRayStash];
+        const double dx = st[3 * kRayStash], dy = st[4 * kRayStash], dz = st[5 * kRayStash];
         const double rx = double(P.x) - ox, ry = double(P.y) - oy, rz = double(P.z) - oz;
         // d . (r3 x r_k) = (d x r3) . r_k: the cross product once for the three
         const double cx = dy * rz - dz * ry, cy = dz * rx - dx * rz, cz = dx * ry - dy * rx;
@@ -483,7 +484,7 @@ __device__ __forceinline__ bool make_ccw64(const Frame& f, float Xx, float Xy, f
 // unsure (given, with PREC false): the step only tests whether its float32
 // decision is unsure -- the test of the precision variant -- and reports it.
 // EXACT (a ray walk of the precision variant): unsure steps are decided along
-// the ray as given (pc.rorig, pc.rdir), else along the float32 basis.
+// the ray as given (pc.ray6), else along the float32 basis.
 template <bool DEPTH, int LAYOUT, bool PREC, bool LINK = false, bool PIPE = false, bool EXACT = false>
 __device__ __forceinline__ void walk_step_rec(const Mem& M, const Frame& f, const Depth& g, Walk& w,
                                               Prec& pc, const Rec& R, Rec* ahead, bool* unsure_out = nullptr) {
@@ -1000,9 +1001,13 @@ __device__ void finish_ray(const DevMesh& m, const Mem& M, const RayArgs& r, int
 // One lane per ray: set-up, walk, result.
 // 8 waves per SIMD (at most 64 VGPRs): the walk is latency-bound, so occupancy
 // is what hides the memory round trips.  The precision variant carries float64
-// code; it runs 7 waves (without tmax) or 5 (with): at these register budgets
-// its step loop keeps every value in registers, and the spilled values are
-// those of the rare float64 paths and of set-up.
+// code; it runs 7 waves (without tmax) or 6 (with): at these register budgets
+// its step loop's common path keeps every value in registers, and the spilled
+// values are those of the rare float64 path and of set-up.  Its float64 path
+// reads the ray from the lane's copy in LDS, so no address stays live for it.
+// At 8 waves without tmax (64 VGPRs) the compiler parks scalar registers in
+// vector-register lanes across the float64 branch, and whole waves came back
+// wrong; 7 waves keep the loop free of such spills.
 // The dispatcher deals blocks to the XCDs round-robin (block b runs on XCD
 // b mod X), and each XCD has an L2 of its own.  Renumbering blocks so that
 // consecutive ones share an XCD keeps neighbouring rays -- which visit the same
@@ -1059,10 +1064,11 @@ __device__ __forceinline__ int32_t wave_min_i(int32_t x) {
 }
 
 // Moller-Trumbore in float64 from the float32 points; false when the line misses
-// the closed triangle or the plane is parallel.
-__device__ __forceinline__ bool mt64(const Mem& M, const int4 fv, double ox, double oy, double oz, double dx,
-                                     double dy, double dz, double& t, double& u, double& v) {
-    const float4 A = load_pt(M, uint32_t(fv.x)), B = load_pt(M, uint32_t(fv.y)), C = load_pt(M, uint32_t(fv.z));
+// the closed triangle or the plane is parallel.  No fused multiply-adds, so every
+// caller rounds alike.
+__device__ __forceinline__ bool mt64_tri(float4 A, float4 B, float4 C, double ox, double oy, double oz, double dx,
+                                         double dy, double dz, double& t, double& u, double& v) {
+#pragma clang fp contract(off)
     const double e1x = double(B.x) - A.x, e1y = double(B.y) - A.y, e1z = double(B.z) - A.z;
     const double e2x = double(C.x) - A.x, e2y = double(C.y) - A.y, e2z = double(C.z) - A.z;
     const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
@@ -1074,6 +1080,12 @@ __device__ __forceinline__ bool mt64(const Mem& M, const int4 fv, double ox, dou
     v = (dx * qx + dy * qy + dz * qz) / det;
     t = (e2x * qx + e2y * qy + e2z * qz) / det;
     return u >= 0.0 && v >= 0.0 && u + v <= 1.0;
+}
+
+__device__ __forceinline__ bool mt64(const Mem& M, const int4 fv, double ox, double oy, double oz, double dx,
+                                     double dy, double dz, double& t, double& u, double& v) {
+    return mt64_tri(load_pt(M, uint32_t(fv.x)), load_pt(M, uint32_t(fv.y)), load_pt(M, uint32_t(fv.z)), ox, oy, oz,
+                    dx, dy, dz, t, u, v);
 }
 
 __device__ DefHit wave_closest_hit(const DevMesh& m, const Mem& M, double ox, double oy, double oz, double dx,
@@ -1185,65 +1197,129 @@ __device__ void list_or_resolve_ties(const DevMesh& m, const Mem& M, const RayAr
     resolve_ties<TMAX>(m, M, r, own, i, steps, n64);
 }
 
-// Grid-wide closest hit by definition of the listed ties: work item k * S + s
-// scans slice s of the constrained triangles (kTieSlice each) for tie k.  Pass 0
-// takes the nearest t (atomic minimum on its bits), pass 1 the lowest id hit
-// within 1e-12 of it; the same rules as wave_closest_hit, so the results are
-// those the wave would write.
-constexpr int kTieSlice = 1024;
+// Grid-wide closest hit by definition of the listed ties.  Work item (b, c) tests
+// the constrained triangles of slice b (one per thread) against the ties of chunk
+// c (staged in LDS).  A tie whose segment (0, t limit] misses the slice's
+// bounding box, padded by 1e-6 of its coordinates' size, skips the slice: a hit
+// that mt64 reports lies within float64 rounding of its triangle, so skipping
+// changes no result.  Pass 0 takes the nearest t (atomic minimum on its bits),
+// pass 1 the lowest id hit within 1e-12 of it; the rules of wave_closest_hit,
+// so the results are those the wave would write.
+constexpr int kTieChunk = 64;
+
+// Whether the segment o + t d, t in [0, tl], meets the box [lo, hi]; a NaN
+// anywhere reads as a miss.
+__device__ __forceinline__ bool segment_meets_box(const double o[3], const double d[3], double tl, const double lo[3],
+                                                  const double hi[3]) {
+    double t0 = 0.0, t1 = tl;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (!(o[a] >= lo[a] && o[a] <= hi[a])) return false;
+            continue;
+        }
+        const double inv = 1.0 / d[a];
+        const double ta = (lo[a] - o[a]) * inv, tb = (hi[a] - o[a]) * inv;
+        t0 = fmax(t0, fmin(ta, tb));
+        t1 = fmin(t1, fmax(ta, tb));
+    }
+    return t0 <= t1;
+}
 
 template <bool TMAX, int LAYOUT>
 __global__ void __launch_bounds__(256) k_tie_scan(DevMesh m, RayArgs r, TieList L, int32_t pass) {
-    __shared__ double red_t[4];
-    __shared__ int32_t red_i[4];
+    __shared__ double s_o[3][kTieChunk], s_d[3][kTieChunk], s_tl[kTieChunk];
+    __shared__ int32_t s_sf[kTieChunk];
+    __shared__ float s_box[4][6];
     const Mem M = make_mem<LAYOUT>(m);
-    const int64_t n = min(*L.count, L.cap);
-    const int64_t slices = (int64_t(m.ntri) + kTieSlice - 1) / kTieSlice;
+    const int32_t n = int32_t(min(*L.count, L.cap));
+    const int32_t nb = (m.ntri + 255) / 256, nc = (n + kTieChunk - 1) / kTieChunk;
     const int4* cfv = reinterpret_cast<const int4*>(m.cfv);
     const int w = int(threadIdx.x >> 6);
-    for (int64_t it = blockIdx.x; it < n * slices; it += gridDim.x) {
-        const int64_t k = it / slices;
-        const int32_t f0 = int32_t((it % slices) * kTieSlice);
-        const int32_t f1 = min(f0 + kTieSlice, m.ntri);
-        const int64_t ray = L.ray[k];
-        const double ox = r.orig[3 * ray], oy = r.orig[3 * ray + 1], oz = r.orig[3 * ray + 2];
-        const double dx = r.dir[3 * ray], dy = r.dir[3 * ray + 1], dz = r.dir[3 * ray + 2];
-        const double tmax = (TMAX && r.tmax) ? double(r.tmax[ray]) : INFINITY;
-        const int32_t sf = r.start_face ? r.start_face[ray] : -1;
-        if (pass == 0) {
-            double best = INFINITY;
-            for (int32_t f = f0 + int32_t(threadIdx.x); f < f1; f += 256) {
-                double t, u, v;
-                if (f != sf && mt64(M, cfv[f], ox, oy, oz, dx, dy, dz, t, u, v) && t > 0.0 && t <= tmax)
-                    best = fmin(best, t);
-            }
-            best = wave_min(best);
-            if ((threadIdx.x & 63) == 0) red_t[w] = best;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                const double b = fmin(fmin(red_t[0], red_t[1]), fmin(red_t[2], red_t[3]));
-                if (b < INFINITY) atomicMin(L.tmin + k, static_cast<unsigned long long>(__double_as_longlong(b)));
-            }
-            __syncthreads();
-        } else {
-            const double tmin = __longlong_as_double(static_cast<long long>(L.tmin[k]));
-            if (!(tmin < INFINITY)) continue;   // the same for the whole block
-            int32_t id = 0x7FFFFFFF;
-            for (int32_t f = f0 + int32_t(threadIdx.x); f < f1; f += 256) {
-                double t, u, v;
-                if (f != sf && mt64(M, cfv[f], ox, oy, oz, dx, dy, dz, t, u, v) && t > 0.0 && t <= tmax &&
-                    t <= tmin + 1e-12)
-                    id = min(id, f);
-            }
-            id = wave_min_i(id);
-            if ((threadIdx.x & 63) == 0) red_i[w] = id;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                const int32_t b = min(min(red_i[0], red_i[1]), min(red_i[2], red_i[3]));
-                if (b != 0x7FFFFFFF) atomicMin(L.best + k, b);
-            }
-            __syncthreads();
+    for (int32_t it = blockIdx.x; it < nb * nc; it += gridDim.x) {
+        const int32_t b = it % nb, c = it / nb;
+        const int32_t f = b * 256 + int32_t(threadIdx.x);
+        const bool have = f < m.ntri;
+        float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A, C = A;
+        if (have) {
+            const int4 fv = cfv[f];
+            A = load_pt(M, uint32_t(fv.x));
+            B = load_pt(M, uint32_t(fv.y));
+            C = load_pt(M, uint32_t(fv.z));
         }
+        // the slice's bounding box
+        float bx[6] = {fminf(A.x, fminf(B.x, C.x)), fminf(A.y, fminf(B.y, C.y)), fminf(A.z, fminf(B.z, C.z)),
+                       -fmaxf(A.x, fmaxf(B.x, C.x)), -fmaxf(A.y, fmaxf(B.y, C.y)), -fmaxf(A.z, fmaxf(B.z, C.z))};
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            float x = have ? bx[e] : INFINITY;
+#pragma unroll
+            for (int k = 32; k >= 1; k >>= 1) x = fminf(x, __shfl_xor(x, k, 64));
+            if ((threadIdx.x & 63) == 0) s_box[w][e] = x;
+        }
+        // the chunk's ties: origin, direction, the limit on t (negative: nothing to find)
+        if (threadIdx.x < kTieChunk) {
+            const int32_t k = c * kTieChunk + int32_t(threadIdx.x);
+            if (k < n) {
+                const int64_t ray = L.ray[k];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    s_o[a][threadIdx.x] = r.orig[3 * ray + a];
+                    s_d[a][threadIdx.x] = r.dir[3 * ray + a];
+                }
+                double tl = (TMAX && r.tmax) ? double(r.tmax[ray]) : INFINITY;
+                if (pass == 1) {
+                    const double tmin = __longlong_as_double(static_cast<long long>(L.tmin[k]));
+                    tl = tmin < INFINITY ? fmin(tl, tmin + 1e-12) : -1.0;
+                }
+                s_tl[threadIdx.x] = tl;
+                s_sf[threadIdx.x] = r.start_face ? r.start_face[ray] : -1;
+            }
+        }
+        __syncthreads();
+        double lo[3], hi[3];
+        double size = 1.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(fminf(s_box[0][a], s_box[1][a]), fminf(s_box[2][a], s_box[3][a]));
+            hi[a] = -fminf(fminf(s_box[0][a + 3], s_box[1][a + 3]), fminf(s_box[2][a + 3], s_box[3][a + 3]));
+            size = fmax(size, fmax(fabs(lo[a]), fabs(hi[a])));
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] -= 1e-6 * size;
+            hi[a] += 1e-6 * size;
+        }
+        // lane j tests tie j against the box; the wave then runs the exact test for
+        // the ties that meet it, one after the other
+        const int32_t kn = min(kTieChunk, n - c * kTieChunk);
+        const int ln = int(threadIdx.x & 63);
+        bool meets = false;
+        if (ln < kn && s_tl[ln] > 0.0) {
+            const double o[3] = {s_o[0][ln], s_o[1][ln], s_o[2][ln]};
+            const double d[3] = {s_d[0][ln], s_d[1][ln], s_d[2][ln]};
+            meets = segment_meets_box(o, d, s_tl[ln], lo, hi);
+        }
+        for (uint64_t J = lanes(meets); J; J &= J - 1) {
+            const int32_t j = __builtin_ctzll(J);
+            const double tl = s_tl[j];
+            const double o[3] = {s_o[0][j], s_o[1][j], s_o[2][j]};
+            const double d[3] = {s_d[0][j], s_d[1][j], s_d[2][j]};
+            double t, u, v;
+            const bool hit = have && f != s_sf[j] && mt64_tri(A, B, C, o[0], o[1], o[2], d[0], d[1], d[2], t, u, v) &&
+                             t > 0.0 && t <= tl;
+            if (!lanes(hit)) continue;
+            const int32_t k = c * kTieChunk + j;
+            if (pass == 0) {
+                const double best = wave_min(hit ? t : INFINITY);
+                if ((threadIdx.x & 63) == 0)
+                    atomicMin(L.tmin + k, static_cast<unsigned long long>(__double_as_longlong(best)));
+            } else {
+                const int32_t id = wave_min_i(hit ? f : 0x7FFFFFFF);
+                if ((threadIdx.x & 63) == 0) atomicMin(L.best + k, id);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -1288,11 +1364,16 @@ __device__ __forceinline__ bool trace_prec(const DevMesh& m, const Mem& M, const
         if (DEFER) { *deferred = true; return false; }
         return true;
     }
-    // float64 decisions along the ray as given (read back when a step is unsure)
+    // float64 decisions along the ray as given, from the lane's copy of it in LDS
+    // (read back when a step is unsure: one LDS round trip, no address to keep)
+    __shared__ float ray_stash[6][kRayStash];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ray_stash[c][threadIdx.x] = r.orig[3 * i + c];
+        ray_stash[3 + c][threadIdx.x] = r.dir[3 * i + c];
+    }
     Prec pc{eps, 0.0f, 0.0f, 0.0f, 0};
-    pc.rorig = r.orig;
-    pc.rdir = r.dir;
-    pc.ray = i;
+    pc.ray6 = &ray_stash[0][threadIdx.x];
     pc.allow_degen = false;
     // the pipelined form of walk_ray (next record loaded inside the step)
     if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
@@ -1317,7 +1398,7 @@ __device__ __forceinline__ bool trace_prec(const DevMesh& m, const Mem& M, const
 }
 
 template <bool TMAX, int LAYOUT, bool PREC, bool STEPS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? (TMAX ? 5 : 7) : 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? (TMAX ? 6 : 7) : 8)))
 k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
     const int64_t j = int64_t(xcd_block(blockIdx.x, gridDim.x, xcds, kn.xcd_blocks)) * blockDim.x + threadIdx.x;
     const Mem M = make_mem<LAYOUT>(m);
@@ -1434,7 +1515,7 @@ __global__ void __launch_bounds__(256) k_trace_persistent(DevMesh m, RayArgs r, 
 // PREC: the precision variant with eps (every lane stays to the end, for the
 // ties its wave resolves together).
 template <int LAYOUT, bool STEPS, bool PREC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 5 : 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC ? 6 : 8)))
 k_trace_batch(const Job* __restrict__ jobs, int32_t n_jobs, uint32_t xcds, float eps) {
     const int64_t b = xcd_block(blockIdx.x, gridDim.x, xcds, 0u);
     int lo = 0, hi = n_jobs;
