@@ -1379,14 +1379,17 @@ __device__ __forceinline__ bool trace_prec(const DevMesh& m, const Mem& M, const
     if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
     Rec R = load_rec<LAYOUT>(M, s.w.next);
     bool unsure = false;
-    while (!pc.degen && walk_on<TMAX>(s, r.max_steps)) {
-        if (DEFER) {
+    if (DEFER) {
+        while (walk_on<TMAX>(s, r.max_steps)) {
             walk_step_rec<TMAX, LAYOUT, false, true, true>(M, s.f, s.g, s.w, pc, R, &R, &unsure);
             if (unsure) break;
-        } else {
-            walk_step_rec<TMAX, LAYOUT, true, true, true, true>(M, s.f, s.g, s.w, pc, R, &R);
+            ++s.steps;
         }
-        ++s.steps;
+    } else if (walk_on<TMAX>(s, r.max_steps)) {
+        do {
+            walk_step_rec<TMAX, LAYOUT, true, true, true, true>(M, s.f, s.g, s.w, pc, R, &R);
+            ++s.steps;
+        } while (!pc.degen && walk_on<TMAX>(s, r.max_steps));
     }
     if (LAYOUT == kTet16) s.w.cur ^= int32_t(s.w.next);
     steps_out = s.steps;
