@@ -1202,7 +1202,10 @@ __device__ void list_or_resolve_ties(const DevMesh& m, const Mem& M, const RayAr
 // c (staged in LDS).  A tie whose segment (0, t limit] misses the slice's
 // bounding box, padded by 1e-6 of its coordinates' size, skips the slice: a hit
 // that mt64 reports lies within float64 rounding of its triangle, so skipping
-// changes no result.  Pass 0 takes the nearest t (atomic minimum on its bits),
+// changes no result.  (The exception would be a ray within about 1e-15 of
+// parallel to a triangle's plane, where the quotients by a near-zero
+// determinant lose their digits; an exactly coplanar ray has a zero
+// determinant and no hit.)  Pass 0 takes the nearest t (atomic minimum on its bits),
 // pass 1 the lowest id hit within 1e-12 of it; the rules of wave_closest_hit,
 // so the results are those the wave would write.
 constexpr int kTieChunk = 64;
