@@ -95,7 +95,7 @@ typedef struct {
     int32_t validate;  /* 1 = check the mesh before packing (recommended) */
     int32_t seed_grid; /* cells per axis of the point-location seed grid; 0 = automatic */
     int64_t bin_rays;  /* rays the handle's own workspace serves (8 bytes each and about
-                          58 KB), allocated here, once; 0 = none.  trace_closest uses it for
+                          400 KB), allocated here, once; 0 = none.  trace_closest uses it for
                           binning, the queue kernel and the precision variant's tie list
                           and two passes when the caller passes no workspace of its own.
                           0 <= bin_rays < 2^31 */
@@ -273,8 +273,8 @@ int trace_closest(tm_mesh m, int64_t n_rays, const float* d_orig, const float* d
  * fixed array of the library instead (4 bytes per ray, at most
  * TM_NOALLOC_MAX_BINNED_RAYS rays: more is TM_ERR_ARG), and the queue kernel's
  * counters (kernel = 3) and the precision variant's tie list (eps > 0) go to
- * 64 KiB beside that room.  The array exists once per device and lives until
- * the process ends (64 MiB + 64 KiB of device memory on every device the
+ * 512 KiB beside that room.  The array exists once per device and lives until
+ * the process ends (64 MiB + 512 KiB of device memory on every device the
  * library's kernels have run on); it is looked up, not allocated, on a
  * device's first call.  Every call on a device shares it, so calls that use it
  * (binning, kernel 3, eps > 0) and overlap in time on one device (other

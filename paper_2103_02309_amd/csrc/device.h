@@ -76,7 +76,7 @@ struct TieList {
     int32_t* best;              // [cap] the lowest id hit within 1e-12 of it
     uint32_t cap;
 };
-constexpr uint32_t kTieCap = 2048;
+constexpr uint32_t kTieCap = 16384;
 // Bytes of a tie list of kTieCap entries (with its counter), 256-byte aligned parts.
 int64_t tie_workspace_bytes();
 // Carves a tie list out of `bytes` of device memory at p.

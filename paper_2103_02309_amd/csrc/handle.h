@@ -49,7 +49,7 @@ int sort_config(const tm_mesh_s* m, const tm_trace_opts& o, int64_t n, bool has_
 
 // Room beyond the binning permutation in a fixed workspace (the queue kernel's
 // counters and job entry, the precision variant's tie list).
-constexpr int64_t kFixedExtraBytes = 65536;
+constexpr int64_t kFixedExtraBytes = 512 * 1024;
 
 // The body of trace_closest.  fixed_ws (non-null): the binning workspace to
 // use instead of the caller's or the handle's (fixed_ws_bytes long); `name`

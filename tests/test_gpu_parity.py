@@ -420,7 +420,7 @@ def test_handle_workspace_and_no_workspace(tiny_mesh, tetrt):
                 assert np.array_equal(got[k], ref[k], equal_nan=True), k
     # more rays than the handle's workspace holds: refused when asked for
     with pytest.raises(tetrt.TetRTError, match="workspace"):
-        big = 2 * n + 32768                       # past all the handle's workspace holds
+        big = 2 * n + (1 << 18)                   # past all the handle's workspace holds (2n + ~100K)
         O2, D2 = _dev(np.resize(o, (big, 3))), _dev(np.resize(d, (big, 3)))
         _raw_trace(tetrt, ws_mesh.handle, O2, D2, _dev(np.resize(tm, big)),
                    tetrt.outputs(big, "cuda:0"), sort=2)
