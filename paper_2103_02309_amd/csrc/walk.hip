@@ -1040,7 +1040,8 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t 
 // the walk undefined -- takes the closest hit by its definition instead: FP64
 // Moller-Trumbore over every constrained triangle (inclusive edges, t in
 // (0, tmax], the start face excluded, hits within 1e-12 of the nearest going to
-// the lowest id), computed by the whole wave together.  So does a ray whose
+// the lowest id): listed and computed by the whole grid (k_tie_scan) when a
+// workspace holds the list, else by the ray's wave together.  So does a ray whose
 // origin lies on the mesh boundary (within 1e-6 of the bounds) where location
 // finds no start tet.
 
@@ -1418,7 +1419,8 @@ k_trace(DevMesh m, RayArgs r, uint32_t xcds, Knobs kn) {
         finish_ray<TMAX>(m, M, r, i, s);
         return;
     }
-    // precision variant: every lane stays to the end (ties are resolved by the wave)
+    // precision variant: every lane stays to the end (ties are listed for the grid,
+    // or, past the list or without one, resolved by the wave)
     const int64_t i = j < r.n ? (r.perm ? int64_t(r.perm[j]) : j) : -1;
     const bool valid = j < r.n && uint64_t(i) < uint64_t(r.n);
     int32_t steps = 0, n64 = 0;
