@@ -113,6 +113,30 @@ def test_primary_sampled_vs_oracle(paper):
     assert rep["ok"], ("eps 1e-6", rep)
 
 
+def test_plane_rays_vs_oracle(paper):
+    """The camera rays that lie exactly in the plane x = y (every one of them,
+    1,080 rays through the grid's diagonal faces; the 607 that reach the cube's
+    unjittered far boundary are this workload's exact float64 ties, answered by
+    the grid tie scan), traced by the precision variant: identical to the
+    oracle, ray for ray (the standard bar, 99.99% of 1,080)."""
+    m, mesh, om, o, d, got = paper
+    idx = np.nonzero(d[:, 0] == d[:, 1])[0]
+    assert idx.size == 1080
+    cam = om.locate(o[:1])
+    ref = om.trace(o[idx], d[idx], start_tet=np.full(idx.size, cam[0], np.int32))
+    O, D = torch.from_numpy(o[idx]).cuda(), torch.from_numpy(d[idx]).cuda()
+    res = mesh.trace(O, D, eps=1e-6, want_fp64=True)
+    torch.cuda.synchronize()
+    sub = {k: v.cpu().numpy() for k, v in res.items()}
+    rep = compare(m.points, om.tri_verts, o[idx], d[idx], ref, sub)
+    assert rep["ok"], rep
+    # the same rays among all 2M of the benchmark's launch give the same answers
+    res = mesh.trace(torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda(), eps=1e-6)
+    torch.cuda.synchronize()
+    for k in ("tri", "t", "bary"):
+        assert np.array_equal(res[k].cpu().numpy()[idx], sub[k], equal_nan=True), k
+
+
 def test_ao_sampled_vs_oracle(paper):
     """AO rays built from oracle hits of a primary sample."""
     m, mesh, om, o, d, got = paper
