@@ -157,8 +157,9 @@ typedef struct {
                             on the ray, a ray in a face's plane) takes the closest hit by
                             its definition (every constrained triangle tested in float64,
                             the lowest id among hits within 1e-12 of the nearest), found by
-                            the whole grid when a workspace holds the tie list, else by the
-                            ray's wave; the results are the same.  With the scene extent 1,
+                            the whole grid for up to 16,384 ties per call when a workspace
+                            holds the tie list, else (and past that) by the ray's wave; the
+                            results are the same.  With the scene extent 1,
                             eps >= 1e-6 covers float32 rounding */
     void* workspace;     /* device scratch for binning, kernel 3's queue and the precision
                             variant's lists (tetmesh_trace_workspace gives the need), or
